@@ -1,0 +1,133 @@
+/*
+ * thinfilm.h -- C ABI of libthinfilm, an MI355X (gfx950) FP64 implementation of the
+ * ADI-Newton time step for the thin-film equation
+ *
+ *     h_t + div[ f0(h) grad lap h + f1(h) grad h ] = 0,
+ *     f0 = h^3,  f1 = kappa h^3 f'(h),  f(h) = (b/h)^n - (b/h)^m,
+ *
+ * on a cell-centred grid with no-flux boundaries (u_n = u_nnn = 0), following
+ * M.-A. Y.-H. Lam, L. J. Cummings, L. Kondic, "Computing dynamics of thin films via
+ * large scale GPU-based simulations", arXiv:1806.10550:
+ *   - flux-form discretisation: Sec. "Conservation Law" (eq. GovEqnCell2) and
+ *     Sec. "Flux Discretization" (face values of f0, f1 are means of the two cells);
+ *   - boundary conditions: Sec. "Boundary Conditions" (even-reflection ghost cells);
+ *   - time stepping: the theta scheme G(u) = u - u^n + dt[theta D(u) + (1-theta) D(u^n)]
+ *     (theta = 1/2 is eq. TrapRule; theta = 1 is backward Euler);
+ *   - Newton iteration with the ADI factorisation (I + c J_y)(I + c J_x), c = theta dt,
+ *     y solve first, mixed terms left in the residual: eqs. DirectionSplit and
+ *     JacobianSystem1-3;
+ *   - acceptance test max|v/u_k| < tol (eq. NewtonError) and the adaptive time-step
+ *     control of Fig. FlowChartTime.
+ *
+ * Memory: every array argument marked "device" is a pointer into HIP device memory
+ * on the device that was current when the grid was created; "host" pointers are
+ * ordinary host memory. Grids are row-major: h[j*nx + i], i along x, j along y,
+ * contiguous, FP64. The caller owns all arrays it passes; the library owns its
+ * scratch buffers and frees them in tf_destroy. All work is enqueued on the stream
+ * given to tf_create; calls that make a host-side decision synchronise that stream.
+ *
+ * Errors: every call returns a tf_status; TF_OK is 0. On any error the bound state
+ * is left at the last accepted time level. tf_last_error() describes the most recent
+ * failure of the calling thread. No C++ exception crosses this interface.
+ * A grid must not be used from two threads at once.
+ */
+#ifndef THINFILM_H
+#define THINFILM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int tf_status;
+enum {
+    TF_OK = 0,
+    TF_EINVAL = 1,   /* bad argument */
+    TF_ENOMEM = 2,   /* device or pinned-host allocation failed */
+    TF_EDEVICE = 3,  /* a HIP call failed; see tf_last_error() */
+    TF_ENOCONV = 4,  /* Newton did not converge and dt fell below dt_min (or adaptive == 0) */
+    TF_ENONPOS = 5,  /* the state holds h <= 0 or NaN */
+    TF_ESTATE = 6    /* no state bound, or model not set */
+};
+
+typedef struct tf_grid tf_grid;
+
+/* Time-stepping scheme and the control of Fig. FlowChartTime.
+ *   theta      1 = backward Euler, 0.5 = trapezoidal rule (eq. TrapRule); 0.5 <= theta <= 1
+ *   tol        accept when max|v/u_k| < tol (eq. NewtonError)
+ *   max_newton iterations per attempt (the paper's K)
+ *   adaptive   0: a non-converged attempt fails the step with TF_ENOCONV;
+ *              1: it is retried with dt *= dt_shrink until dt < dt_min (TF_ENOCONV);
+ *                 after grow_after consecutive accepted steps dt = min(dt*dt_grow, dt_max). */
+typedef struct {
+    double theta, tol, dt_min, dt_max, dt_shrink, dt_grow;
+    int max_newton, grow_after, adaptive;
+} tf_scheme;
+
+/* Per accepted step: time after the step, the dt it used, the final update ratio
+ * max|v/u_k| and residual max|G|, Newton iterations of the accepted attempt, the
+ * number of rejected attempts, the status, and (only when mass diagnostics are on,
+ * see tf_set_diagnostics) the compensated sum of h and its minimum. */
+typedef struct {
+    double t, dt_used, e_final, r_final, mass, hmin;
+    int newton_iters, rejections, status, total_iters;
+} tf_step_info;
+
+/* Create a grid of nx x ny cells of side ds (nx, ny >= 4, ds > 0) whose work is
+ * enqueued on `stream` (a hipStream_t; NULL = the default stream). Allocates the
+ * device scratch (about 5 fields of nx*ny doubles). Default scheme: theta = 1,
+ * tol = 1e-10, max_newton = 5000, adaptive = 0, dt_min = 1e-6, dt_max = 1,
+ * dt_shrink = 0.5, dt_grow = 1.1, grow_after = 5. */
+tf_status tf_create(int nx, int ny, double ds, void *stream, tf_grid **out);
+tf_status tf_destroy(tf_grid *g);
+
+/* Power-law model: f = (b/h)^n - (b/h)^m, f1 = kappa h^3 f'(h) (eq. GeneralDisPreForm
+ * with the power-law term of eq. DisjPressNLC). b > 0; n and m integral with
+ * 16 >= n > m >= 1 (TF_EINVAL otherwise). kappa may have any sign. */
+tf_status tf_set_model(tf_grid *g, double kappa, double b, double n, double m);
+tf_status tf_set_scheme(tf_grid *g, const tf_scheme *s);
+tf_status tf_get_scheme(const tf_grid *g, tf_scheme *s);
+/* 1: fill tf_step_info.mass / hmin after every accepted step (one extra read of h). */
+tf_status tf_set_diagnostics(tf_grid *g, int mass_every_step);
+
+/* Borrow the caller's state h (device, nx*ny FP64). The library reads and writes it
+ * in place; during a call it may also hold iterates there. It must stay allocated
+ * until unbound (tf_bind_state(g, NULL)) or tf_destroy. Resets the time to 0. */
+tf_status tf_bind_state(tf_grid *g, double *h_dev);
+
+/* Advance the bound state by exactly one accepted step. *dt_inout: dt to try in,
+ * dt for the next step out. info may be NULL. TF_ENONPOS if the state holds h <= 0
+ * or NaN; TF_ENOCONV as in tf_scheme. */
+tf_status tf_step(tf_grid *g, double *dt_inout, tf_step_info *info);
+/* nsteps accepted steps; log (host, nsteps entries) may be NULL. Stops at the first
+ * failure, leaving h at the last accepted state. */
+tf_status tf_advance(tf_grid *g, int nsteps, double *dt_inout, tf_step_info *log);
+
+/* Compensated sum of h and its minimum (Sec. "Conservation of Mass"); host outputs. */
+tf_status tf_mass(tf_grid *g, double *mass, double *hmin);
+
+/* One raw ADI-Newton iteration (eqs. JacobianSystem1-3) on caller buffers (device,
+ * nx*ny each): u_kp1 = u_k + v with the grid's model and theta, for time step dt and
+ * previous level u_n. Host outputs: e = max|v/u_k|, r = max|G(u_k)|, flags bit 0 =
+ * an iterate value <= 0, bit 1 = NaN. u_kp1 must not alias u_k or u_n. */
+tf_status tf_newton_iteration(tf_grid *g, const double *u_n, const double *u_k, double *u_kp1, double dt,
+                              double *e, double *r, int *flags);
+/* out = D(u), the flux-difference operator (eq. FluxDiffOper); device arrays. */
+tf_status tf_flux_divergence(tf_grid *g, const double *u, double *out);
+
+/* Per-kernel timing with HIP events recorded on the grid's stream around every
+ * launch. tf_profile(g, 1) starts (and clears) recording; tf_profile_read fills
+ * total milliseconds and launch counts for each kernel class in the order of
+ * tf_profile_names() (comma-separated), up to n classes, and returns the number of
+ * classes. */
+tf_status tf_profile(tf_grid *g, int on);
+int tf_profile_read(tf_grid *g, double *ms, long *count, int n);
+const char *tf_profile_names(void);
+
+/* Description of the calling thread's most recent error (never NULL). */
+const char *tf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* THINFILM_H */

@@ -1,0 +1,87 @@
+// Internal declarations shared by the HIP kernels (tf_kernels.hip) and the host
+// runtime (tf_api.hip) of libthinfilm. Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace tf {
+
+// Geometry of the partitioned line solver.
+//   A line (a grid column for the y sweep, a grid row for the x sweep) is cut into
+//   segments of TILE cells; 64 neighbouring lines times one segment form a tile that
+//   one workgroup owns. Inside a tile each of the NSUB waves eliminates a
+//   sub-segment of at most SUB cells for all 64 lines (one line per lane).
+constexpr int TILE = 64;
+constexpr int NSUB = 4;
+constexpr int SUB = TILE / NSUB;
+constexpr int HALO = 2;
+constexpr int TW = TILE + 2 * HALO;      // haloed tile width (68)
+constexpr int UPITCH = TW + 1;           // LDS row pitch of the haloed u tile (odd: no bank conflicts)
+constexpr int WPITCH = TILE + 1;         // LDS row pitch of the second input tile
+constexpr int NREL = 20;                 // doubles per (segment, line) relation record
+constexpr int NEXT = 4;                  // doubles per (segment, line) boundary record
+constexpr int NCHAIN = 12;               // doubles per (segment, line) chain record
+constexpr int BLOCK = 64 * NSUB;
+
+// Segments of a line of n >= 2 cells: TILE cells each, except that a last segment of
+// a single cell borrows one from its neighbour (every segment has >= 2 cells).
+__host__ __device__ inline int seg_count(int n) { return (n + TILE - 1) / TILE; }
+__host__ __device__ inline int seg_start(int q, int n)
+{
+    const int P = seg_count(n);
+    if (q >= P) return n;
+    int s = q * TILE;
+    if (q == P - 1 && P > 1 && n - s < 2) s -= 1;
+    return s;
+}
+
+// Power-law model f0 = h^3, f1 = kappa h^3 f'(h), f = (b/h)^n - (b/h)^m with integer n, m.
+// In terms of r = 1/h:
+//   f1  = Cm r^(m-2) - Cn r^(n-2),  Cm = kappa m b^m, Cn = kappa n b^n
+//   f1' = Dn r^(n-1) - Dm r^(m-1),  Dn = kappa n (n-2) b^n, Dm = kappa m (m-2) b^m
+struct Model {
+    double kappa, b;
+    int n, m;
+    double Cn, Cm, Dn, Dm;
+    bool p32; // n == 3 && m == 2: f1 = Cm - Cn r, f1' = Dn r^2
+};
+
+// Parameters of one sweep pass (K1 relations / K3 solve) over a grid or a packed film.
+struct PassParams {
+    int nx, ny;
+    double ids, ids2;   // 1/ds, 1/ds^2
+    double k1, k3;      // c/ds, c/ds^4 with c = theta dt (band scale)
+    double cD;          // theta dt (scale of D(u_k) in the residual)
+    Model M;
+    const double *u;    // u_k
+    const double *in2;  // y sweep: b^n (= u^n for backward Euler); x sweep: w
+    double *out;        // y sweep: w; x sweep: u_{k+1}
+    double *rel;        // [P][NREL][nlines]
+    const double *ext;  // [P][NEXT][nlines]
+    unsigned long long *res;        // reduction slot {emax, rmax, flags, ...}
+    unsigned long long *res_clear;  // slot zeroed by block 0 (may be null)
+    int tiles_x, tiles_y;
+};
+
+struct ChainParams {
+    int nlines, P;
+    const double *rel;
+    double *chain;
+    double *ext;
+};
+
+enum ResultWord { RES_EMAX = 0, RES_RMAX = 1, RES_FLAGS = 2, RES_WORDS = 8 };
+enum ResultFlag { FLAG_NONPOS = 1, FLAG_NAN = 2 };
+
+// Launchers (tf_kernels.hip). Each returns the launch status.
+hipError_t launch_pass(int dir, bool solve, const PassParams &p, hipStream_t s);
+hipError_t launch_chain(const ChainParams &c, hipStream_t s);
+hipError_t launch_flux_divergence(int nx, int ny, double ids, double ids2, const Model &M,
+                                  const double *u, double alpha, double beta, const double *add,
+                                  double *out, hipStream_t s);
+hipError_t launch_mass(const double *u, size_t n, double *partials, int nblocks, hipStream_t s);
+int mass_blocks(size_t n);
+
+} // namespace tf

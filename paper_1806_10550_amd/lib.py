@@ -1,0 +1,207 @@
+"""ctypes binding of libthinfilm (include/thinfilm.h): argument marshalling only.
+
+Every step of the ADI-Newton path runs in the HIP library; PyTorch supplies device
+memory (contiguous float64 CUDA tensors) and the stream. If the built library is
+missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libthinfilm.so")
+
+TF_OK, TF_EINVAL, TF_ENOMEM, TF_EDEVICE, TF_ENOCONV, TF_ENONPOS, TF_ESTATE = range(7)
+STATUS_NAMES = {0: "TF_OK", 1: "TF_EINVAL", 2: "TF_ENOMEM", 3: "TF_EDEVICE", 4: "TF_ENOCONV",
+                5: "TF_ENONPOS", 6: "TF_ESTATE"}
+
+
+class Scheme(C.Structure):
+    """tf_scheme: theta scheme and the dt control of Fig. FlowChartTime."""
+    _fields_ = [("theta", C.c_double), ("tol", C.c_double), ("dt_min", C.c_double),
+                ("dt_max", C.c_double), ("dt_shrink", C.c_double), ("dt_grow", C.c_double),
+                ("max_newton", C.c_int), ("grow_after", C.c_int), ("adaptive", C.c_int)]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt_used", C.c_double), ("e_final", C.c_double),
+                ("r_final", C.c_double), ("mass", C.c_double), ("hmin", C.c_double),
+                ("newton_iters", C.c_int), ("rejections", C.c_int), ("status", C.c_int),
+                ("total_iters", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; "
+                               f"g.build()'` (or python paper_1806_10550_amd/build.py) first")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        D = C.c_double
+        L.tf_last_error.restype = C.c_char_p
+        L.tf_profile_names.restype = C.c_char_p
+        L.tf_create.argtypes = [C.c_int, C.c_int, D, P, C.POINTER(P)]
+        L.tf_destroy.argtypes = [P]
+        L.tf_set_model.argtypes = [P, D, D, D, D]
+        L.tf_set_scheme.argtypes = [P, C.POINTER(Scheme)]
+        L.tf_get_scheme.argtypes = [P, C.POINTER(Scheme)]
+        L.tf_set_diagnostics.argtypes = [P, C.c_int]
+        L.tf_bind_state.argtypes = [P, P]
+        L.tf_step.argtypes = [P, C.POINTER(D), C.POINTER(StepInfo)]
+        L.tf_advance.argtypes = [P, C.c_int, C.POINTER(D), P]
+        L.tf_mass.argtypes = [P, C.POINTER(D), C.POINTER(D)]
+        L.tf_newton_iteration.argtypes = [P, P, P, P, D, C.POINTER(D), C.POINTER(D), C.POINTER(C.c_int)]
+        L.tf_flux_divergence.argtypes = [P, P, P]
+        L.tf_profile.argtypes = [P, C.c_int]
+        L.tf_profile_read.argtypes = [P, C.POINTER(D), C.POINTER(C.c_long), C.c_int]
+        L.tf_profile_read.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != TF_OK:
+        raise TFError(st, lib().tf_last_error().decode())
+
+
+def _ptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64 \
+            or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def default_scheme(**kw) -> Scheme:
+    s = Scheme(1.0, 1e-10, 1e-6, 1.0, 0.5, 1.1, 5000, 5, 0)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+@dataclass
+class StepResult:
+    dt_next: float
+    info: dict
+
+
+class Grid:
+    """One film of nx x ny cells of side ds; see include/thinfilm.h."""
+
+    def __init__(self, nx: int, ny: int, ds: float, stream=None):
+        self._h = C.c_void_p()
+        _check(lib().tf_create(int(nx), int(ny), float(ds), _stream_ptr(stream), C.byref(self._h)))
+        self.nx, self.ny, self.ds = nx, ny, ds
+        self._state = None
+
+    def close(self):
+        if self._h:
+            lib().tf_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_model(self, kappa=10.0, b=0.1, n=3, m=2):
+        _check(lib().tf_set_model(self._h, float(kappa), float(b), float(n), float(m)))
+        return self
+
+    def set_scheme(self, **kw):
+        s = default_scheme(**kw)
+        _check(lib().tf_set_scheme(self._h, C.byref(s)))
+        return self
+
+    def scheme(self) -> Scheme:
+        s = Scheme()
+        _check(lib().tf_get_scheme(self._h, C.byref(s)))
+        return s
+
+    def set_diagnostics(self, mass_every_step: bool):
+        _check(lib().tf_set_diagnostics(self._h, int(bool(mass_every_step))))
+
+    def bind(self, h):
+        """Bind a contiguous (ny, nx) float64 CUDA tensor as the state (borrowed)."""
+        if tuple(h.shape) != (self.ny, self.nx):
+            raise ValueError(f"state must have shape ({self.ny}, {self.nx})")
+        _check(lib().tf_bind_state(self._h, _ptr(h)))
+        self._state = h
+        return self
+
+    def step(self, dt: float) -> StepResult:
+        d = C.c_double(dt)
+        info = StepInfo()
+        _check(lib().tf_step(self._h, C.byref(d), C.byref(info)))
+        return StepResult(d.value, info.as_dict())
+
+    def advance(self, nsteps: int, dt: float, log: bool = False):
+        d = C.c_double(dt)
+        arr = (StepInfo * max(nsteps, 1))() if log else None
+        st = lib().tf_advance(self._h, int(nsteps), C.byref(d),
+                              C.cast(arr, C.c_void_p) if log else None)
+        infos = [arr[i].as_dict() for i in range(nsteps)] if log else None
+        _check(st)
+        return d.value, infos
+
+    def try_advance(self, nsteps: int, dt: float):
+        """Like advance but returns (status, dt, log) instead of raising."""
+        d = C.c_double(dt)
+        arr = (StepInfo * max(nsteps, 1))()
+        st = lib().tf_advance(self._h, int(nsteps), C.byref(d), C.cast(arr, C.c_void_p))
+        return st, d.value, [arr[i].as_dict() for i in range(nsteps)]
+
+    def try_step(self, dt: float):
+        d = C.c_double(dt)
+        info = StepInfo()
+        st = lib().tf_step(self._h, C.byref(d), C.byref(info))
+        return st, d.value, info.as_dict()
+
+    def mass(self):
+        m, hm = C.c_double(), C.c_double()
+        _check(lib().tf_mass(self._h, C.byref(m), C.byref(hm)))
+        return m.value, hm.value
+
+    def newton_iteration(self, un, uk, out, dt: float):
+        e, r, f = C.c_double(), C.c_double(), C.c_int()
+        _check(lib().tf_newton_iteration(self._h, _ptr(un), _ptr(uk), _ptr(out), float(dt),
+                                         C.byref(e), C.byref(r), C.byref(f)))
+        return e.value, r.value, f.value
+
+    def flux_divergence(self, u, out):
+        _check(lib().tf_flux_divergence(self._h, _ptr(u), _ptr(out)))
+        return out
+
+    def profile(self, on: bool):
+        _check(lib().tf_profile(self._h, int(bool(on))))
+
+    def profile_read(self):
+        names = lib().tf_profile_names().decode().split(",")
+        n = len(names)
+        ms = (C.c_double * n)()
+        cnt = (C.c_long * n)()
+        lib().tf_profile_read(self._h, ms, cnt, n)
+        return {names[i]: (ms[i], cnt[i]) for i in range(n)}
