@@ -1,0 +1,160 @@
+"""Throughput benchmark of the FP64 ADI-Newton thin-film step on one MI355X.
+
+Workload (default): the 8192^2 film, L = 256 lambda_m, h0 = 1 + 0.01 U[-1,1] (seed 2),
+backward Euler dt = 0.2, Newton tol 1e-10, fixed dt. A "step" is one accepted time
+step (every Newton iteration of it: residual, y sweep, x sweep, update, reductions).
+W untimed warm-up steps are taken first, then exactly K steps are timed between
+stream synchronisations with the state resident in HBM.
+
+Printed: one JSON line with steps/s, the roofline record of the dominant kernel
+(algorithmic bytes per launch over its mean HIP-event duration) and the oracle's
+rate on the host (a bounded sample, see cpu_baseline.sample).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("ADI steps/s & HBM GB/s (FP64, 2048²/8192²); ensemble + adjoint cost vs forward")
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per cell for each kernel class (one read of each input field and
+# one write of the output field of its sweep); see DESIGN.md "Roofline".
+ALGO_BYTES_PER_CELL = {"relations_y": 16, "solve_y": 24, "relations_x": 16, "solve_x": 24}
+KERNEL_SOURCES = ["paper_1806_10550_amd/csrc/tf_kernels.hip", "paper_1806_10550_amd/csrc/tf_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large8192.json")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, ncells):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when
+    absent or taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or kernel not in t.get("kernels", {}):
+        return None
+    k = t["kernels"][kernel]
+    return (k["fetch_kib"] + k["write_kib"]) * 1024.0 * t.get("copy_scale", 1.0)
+
+
+def cpu_baseline(h_np, ds, dt, iters_per_step):
+    """Oracle (plain C, OpenMP over lines) timed for ONE Newton iteration of the same
+    film; steps/s = 1 / (t_iteration * mean Newton iterations per step of the GPU run)."""
+    from oracle import oracle as orc
+    threads = len(os.sched_getaffinity(0))
+    orc.set_threads(threads)
+    M = orc.Model(kappa=10.0, b=0.1, n=3.0, m=2.0)
+    t0 = time.perf_counter()
+    orc.adi_iteration(M, h_np, h_np, ds, dt, 1.0)
+    t_it = time.perf_counter() - t0
+    return {"value": 1.0 / (t_it * iters_per_step), "unit": "steps/s", "cores": orc.get_threads(),
+            "kind": "oracle",
+            "sample": (f"one Newton iteration on the full {h_np.shape[1]}x{h_np.shape[0]} film "
+                       f"({t_it:.2f} s), scaled by the GPU run's {iters_per_step:.2f} iterations/step")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="large8192")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1806_10550_amd import synth
+    from paper_1806_10550_amd.lib import Grid
+
+    cfg = synth.CONFIGS[args.config]
+    n = cfg.n
+    h_np = cfg.film()
+    dev = torch.device("cuda:0")
+    h = torch.from_numpy(h_np).to(dev)
+    g = Grid(n, n, cfg.ds)
+    g.set_model(cfg.kappa, cfg.b, cfg.nexp, cfg.mexp)
+    g.set_scheme(theta=1.0, tol=cfg.tol, max_newton=5000, adaptive=cfg.adaptive)
+    g.bind(h)
+    dt = cfg.dt
+    if args.warmup > 0:
+        dt, _ = g.advance(args.warmup, dt)
+    torch.cuda.synchronize()
+    g.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dt, log = g.advance(args.steps, dt, log=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = g.profile_read()
+    g.profile(False)
+    iters = [x["newton_iters"] for x in log]
+    total_iters = sum(x["total_iters"] for x in log)
+    ncells = n * n
+    steps_per_s = args.steps / elapsed
+
+    # dominant kernel by total event time
+    dom = max(ALGO_BYTES_PER_CELL, key=lambda k: prof[k][0])
+    ms, cnt = prof[dom]
+    avg_s = ms / 1e3 / max(cnt, 1)
+    algo_bytes = ALGO_BYTES_PER_CELL[dom] * ncells
+    achieved = algo_bytes / avg_s / 1e9
+    traffic = traffic_for(dom, ncells)
+    kernel_ms = sum(v[0] for v in prof.values())
+    iter_frac = (48.0 * ncells * total_iters) / (elapsed * HBM_PEAK_GBS * 1e9)
+
+    out = {
+        "metric": METRIC,
+        "value": steps_per_s,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {n}x{n} film, L=256 lambda_m, noise 0.01 seed {cfg.seed}, "
+                               f"backward Euler dt={cfg.dt}, tol {cfg.tol}, fixed dt",
+                   "nx": n, "ny": n, "dt": cfg.dt, "tol": cfg.tol},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic},
+        "newton_iters_per_step": total_iters / args.steps,
+        "grid_point_steps_per_s": steps_per_s * ncells,
+        "grid_point_iterations_per_s": total_iters * ncells / elapsed,
+        "iteration_roofline_frac": iter_frac,
+        "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
+        "kernel_launches": {k: v[1] for k, v in prof.items()},
+        "kernel_busy_frac": kernel_ms / (1e3 * elapsed),
+    }
+    if not args.no_cpu_baseline:
+        h_now = h.cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(h_now, cfg.ds, dt, total_iters / args.steps)
+    print(json.dumps(out), flush=True)
+    g.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -114,8 +114,6 @@ tf::PassParams base_params(const tf_grid *g, double dt)
     P.k3 = c / (g->ds * g->ds * g->ds * g->ds);
     P.cD = c;
     P.M = g->M;
-    P.tiles_x = g->Px;
-    P.tiles_y = g->Py;
     return P;
 }
 
@@ -136,6 +134,8 @@ tf_status enqueue_iteration(tf_grid *g, const double *bnp, const double *uk, dou
     P.out = g->w;
     P.res = res;
     P.res_clear = clr;
+    P.tiles_x = (g->nx + tf::LT0 - 1) / tf::LT0;
+    P.tiles_y = g->Py;
     if ((st = timed(g, P_REL_Y, [&] { return tf::launch_pass(0, false, P, g->stream); })) != TF_OK) return st;
     tf::ChainParams C{g->nx, g->Py, g->rel, g->chain, g->ext};
     if ((st = timed(g, P_CHAIN_Y, [&] { return tf::launch_chain(C, g->stream); })) != TF_OK) return st;
@@ -145,6 +145,8 @@ tf_status enqueue_iteration(tf_grid *g, const double *bnp, const double *uk, dou
     // x sweep: (I + c J_x) v = w, u_{k+1} = u_k + v
     P.in2 = g->w;
     P.out = ukp1;
+    P.tiles_x = g->Px;
+    P.tiles_y = (g->ny + tf::TILE - 1) / tf::TILE;
     if ((st = timed(g, P_REL_X, [&] { return tf::launch_pass(1, false, P, g->stream); })) != TF_OK) return st;
     tf::ChainParams Cx{g->ny, g->Px, g->rel, g->chain, g->ext};
     if ((st = timed(g, P_CHAIN_X, [&] { return tf::launch_chain(Cx, g->stream); })) != TF_OK) return st;

@@ -20,6 +20,16 @@
 
 namespace tf {
 
+#ifndef K3_WAVES_PER_EU
+#define K3_WAVES_PER_EU 2
+#endif
+#ifndef K1_UNROLL
+#define K1_UNROLL 1
+#endif
+#ifndef K1Y_FAST_UNROLL
+#define K1Y_FAST_UNROLL 8
+#endif
+
 // Reciprocal from the hardware estimate refined by two Newton-Raphson steps
 // r <- r + r (1 - x r); accurate to about one ulp for normal x.
 __device__ __forceinline__ double rcp(double x)
@@ -59,7 +69,7 @@ __device__ __forceinline__ void model_coefs(const Model &M, double u, double &f0
 }
 
 struct Cell {
-    double u, lap, f0, f1, f0p, f1p;
+    double u, lap, f0, f1, f0p, f1p; // f0p, f1p hold f0'/2 and f1'/2
 };
 
 // Even reflection across the boundary faces (no-flux ghosts), clamped so that a
@@ -95,6 +105,8 @@ __device__ __forceinline__ Cell cell_at(const double *sU, const Model &M, double
     }
     c.lap = (xp + xm + yp + ym - 4.0 * c.u) * ids2;
     model_coefs<P32>(M, c.u, c.f0, c.f1, c.f0p, c.f1p);
+    c.f0p *= 0.5; // the bands use f0'/2 and f1'/2
+    c.f1p *= 0.5;
     return c;
 }
 
@@ -130,146 +142,159 @@ struct Rel {
     double T[2][5], B[2][5];
 };
 
-// Numeric interface chain over Q segments with outer boundary values (l, r):
-// eliminates forward keeping T_q = tau_q + N_q T_{q+1}, B_q = bt_q + M_q T_{q+1}.
-// Outputs the boundary values of every segment: lo[q] = B_{q-1}, hi[q] = T_{q+1}.
-template <int QMAX>
-__device__ __forceinline__ void chain_numeric(const Rel *R, int Q, double l1, double l2, double r1,
-                                              double r2, double lo[QMAX][2], double hi[QMAX][2])
+// Relation record q of this lane from the LDS exchange area.
+__device__ __forceinline__ void load_rel(const double *sB, int q, int lane, Rel &S)
 {
-    double tau[QMAX][2], bt[QMAX][2];
-    M2 N[QMAX], Mm[QMAX];
+    const double *src = sB + (size_t)q * NREL * 64 + lane;
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-        if (q >= Q) break;
-        const Rel &S = R[q];
-        const M2 Tl = {S.T[0][1], S.T[0][2], S.T[1][1], S.T[1][2]};
-        const M2 Tr = {S.T[0][3], S.T[0][4], S.T[1][3], S.T[1][4]};
-        const M2 Bl = {S.B[0][1], S.B[0][2], S.B[1][1], S.B[1][2]};
-        const M2 Br = {S.B[0][3], S.B[0][4], S.B[1][3], S.B[1][4]};
-        if (q == 0) {
-            tau[0][0] = S.T[0][0] + Tl.a * l1 + Tl.b * l2;
-            tau[0][1] = S.T[1][0] + Tl.c * l1 + Tl.d * l2;
-            N[0] = Tr;
-            bt[0][0] = S.B[0][0] + Bl.a * l1 + Bl.b * l2;
-            bt[0][1] = S.B[1][0] + Bl.c * l1 + Bl.d * l2;
-            Mm[0] = Br;
-        } else {
-            const M2 K = inv_i_minus(mul(Tl, Mm[q - 1]));
-            const double s0 = S.T[0][0] + Tl.a * bt[q - 1][0] + Tl.b * bt[q - 1][1];
-            const double s1 = S.T[1][0] + Tl.c * bt[q - 1][0] + Tl.d * bt[q - 1][1];
-            tau[q][0] = K.a * s0 + K.b * s1;
-            tau[q][1] = K.c * s0 + K.d * s1;
-            N[q] = mul(K, Tr);
-            const M2 &Mp = Mm[q - 1];
-            const double v0 = bt[q - 1][0] + Mp.a * tau[q][0] + Mp.b * tau[q][1];
-            const double v1 = bt[q - 1][1] + Mp.c * tau[q][0] + Mp.d * tau[q][1];
-            bt[q][0] = S.B[0][0] + Bl.a * v0 + Bl.b * v1;
-            bt[q][1] = S.B[1][0] + Bl.c * v0 + Bl.d * v1;
-            const M2 BM = mul(mul(Bl, Mp), N[q]);
-            Mm[q] = {BM.a + Br.a, BM.b + Br.b, BM.c + Br.c, BM.d + Br.d};
-        }
-    }
-    double tn0 = r1, tn1 = r2;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int q = QMAX - 1; q >= 0; --q) {
-        if (q >= Q) continue;
-        hi[q][0] = tn0;
-        hi[q][1] = tn1;
-        const double t0 = tau[q][0] + N[q].a * tn0 + N[q].b * tn1;
-        const double t1 = tau[q][1] + N[q].c * tn0 + N[q].d * tn1;
-        if (q + 1 < Q) {
-            lo[q + 1][0] = bt[q][0] + Mm[q].a * tn0 + Mm[q].b * tn1;
-            lo[q + 1][1] = bt[q][1] + Mm[q].c * tn0 + Mm[q].d * tn1;
+        for (int j = 0; j < 5; ++j) {
+            S.T[i][j] = src[(i * 5 + j) * 64];
+            S.B[i][j] = src[(10 + i * 5 + j) * 64];
         }
-        tn0 = t0;
-        tn1 = t1;
-    }
-    lo[0][0] = l1;
-    lo[0][1] = l2;
 }
 
-// Symbolic interface chain over Q sub-segments: returns the relation record of the
-// whole segment (top pair of the first sub-segment, bottom pair of the last) in terms
-// of the segment's outer boundary values.
-template <int QMAX>
-__device__ __forceinline__ void chain_symbolic(const Rel *R, int Q, Rel &out)
+// Interface chain over the Q sub-segments of a tile (forward block elimination):
+// with B_{q-1} = bt_{q-1} + M_{q-1} T_q from the previous step, sub-segment q gives
+//   T_q = tau_q + N_q T_{q+1},  tau_q = K (t_q + Tl_q bt_{q-1}),  N_q = K Tr_q,
+//   K = (I - Tl_q M_{q-1})^-1,
+//   B_q = bt_q + M_q T_{q+1},   bt_q = b_q + Bl_q (bt_{q-1} + M_{q-1} tau_q),
+//   M_q = Bl_q M_{q-1} N_q + Br_q.
+// The recurrences below carry only what later steps need, so T_0 (and the boundary
+// values a wave needs) follow from forward accumulation: T_0 = sum_q N_0..N_{q-1} tau_q
+// + N_0..N_{Q-1} T_Q.
+
+// Symbolic version: quantities are affine forms over (1, l1, l2, r1, r2), the tile's
+// outer boundary values. Returns the tile's relation record (T_0, B_{Q-1}).
+__device__ __forceinline__ void chain_symbolic(const double *sB, int lane, int Q, Rel &out)
 {
-    // forms over (1, l1, l2, r1, r2)
-    double tau[QMAX][2][5], bt[QMAX][2][5];
-    M2 N[QMAX], Mm[QMAX];
+    double bt[2][5], acc[2][5];
+    M2 Mm = {0, 0, 0, 0}, P = {1, 0, 0, 1};
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) { bt[i][j] = 0.0; acc[i][j] = 0.0; }
+#pragma unroll
+    for (int q = 0; q < NSUB; ++q) {
         if (q >= Q) break;
-        const Rel &S = R[q];
+        Rel S;
+        load_rel(sB, q, lane, S);
         const M2 Tl = {S.T[0][1], S.T[0][2], S.T[1][1], S.T[1][2]};
         const M2 Tr = {S.T[0][3], S.T[0][4], S.T[1][3], S.T[1][4]};
         const M2 Bl = {S.B[0][1], S.B[0][2], S.B[1][1], S.B[1][2]};
         const M2 Br = {S.B[0][3], S.B[0][4], S.B[1][3], S.B[1][4]};
+        double tau[2][5];
+        M2 N;
         if (q == 0) {
+            // B_{-1} is the outer pair (l1, l2)
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                tau[0][i][0] = S.T[i][0]; tau[0][i][1] = S.T[i][1]; tau[0][i][2] = S.T[i][2];
-                tau[0][i][3] = 0.0; tau[0][i][4] = 0.0;
-                bt[0][i][0] = S.B[i][0]; bt[0][i][1] = S.B[i][1]; bt[0][i][2] = S.B[i][2];
-                bt[0][i][3] = 0.0; bt[0][i][4] = 0.0;
+                tau[i][0] = S.T[i][0]; tau[i][1] = S.T[i][1]; tau[i][2] = S.T[i][2]; tau[i][3] = 0.0; tau[i][4] = 0.0;
+                bt[i][0] = S.B[i][0]; bt[i][1] = S.B[i][1]; bt[i][2] = S.B[i][2]; bt[i][3] = 0.0; bt[i][4] = 0.0;
             }
-            N[0] = Tr;
-            Mm[0] = Br;
+            N = Tr;
+            Mm = Br;
         } else {
-            const M2 K = inv_i_minus(mul(Tl, Mm[q - 1]));
-            double s[2][5];
+            const M2 K = inv_i_minus(mul(Tl, Mm));
+            N = mul(K, Tr);
 #pragma unroll
             for (int j = 0; j < 5; ++j) {
-                s[0][j] = (j == 0 ? S.T[0][0] : 0.0) + Tl.a * bt[q - 1][0][j] + Tl.b * bt[q - 1][1][j];
-                s[1][j] = (j == 0 ? S.T[1][0] : 0.0) + Tl.c * bt[q - 1][0][j] + Tl.d * bt[q - 1][1][j];
+                const double s0 = (j == 0 ? S.T[0][0] : 0.0) + Tl.a * bt[0][j] + Tl.b * bt[1][j];
+                const double s1 = (j == 0 ? S.T[1][0] : 0.0) + Tl.c * bt[0][j] + Tl.d * bt[1][j];
+                tau[0][j] = K.a * s0 + K.b * s1;
+                tau[1][j] = K.c * s0 + K.d * s1;
+                const double v0 = bt[0][j] + Mm.a * tau[0][j] + Mm.b * tau[1][j];
+                const double v1 = bt[1][j] + Mm.c * tau[0][j] + Mm.d * tau[1][j];
+                bt[0][j] = (j == 0 ? S.B[0][0] : 0.0) + Bl.a * v0 + Bl.b * v1;
+                bt[1][j] = (j == 0 ? S.B[1][0] : 0.0) + Bl.c * v0 + Bl.d * v1;
             }
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                tau[q][0][j] = K.a * s[0][j] + K.b * s[1][j];
-                tau[q][1][j] = K.c * s[0][j] + K.d * s[1][j];
-            }
-            N[q] = mul(K, Tr);
-            const M2 &Mp = Mm[q - 1];
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                const double v0 = bt[q - 1][0][j] + Mp.a * tau[q][0][j] + Mp.b * tau[q][1][j];
-                const double v1 = bt[q - 1][1][j] + Mp.c * tau[q][0][j] + Mp.d * tau[q][1][j];
-                bt[q][0][j] = (j == 0 ? S.B[0][0] : 0.0) + Bl.a * v0 + Bl.b * v1;
-                bt[q][1][j] = (j == 0 ? S.B[1][0] : 0.0) + Bl.c * v0 + Bl.d * v1;
-            }
-            const M2 BM = mul(mul(Bl, Mp), N[q]);
-            Mm[q] = {BM.a + Br.a, BM.b + Br.b, BM.c + Br.c, BM.d + Br.d};
-        }
-    }
-    // T_{Q} is the outer right pair: the form (r1, r2)
-    double tn[2][5] = {{0, 0, 0, 1, 0}, {0, 0, 0, 0, 1}};
-#pragma unroll
-    for (int q = QMAX - 1; q >= 0; --q) {
-        if (q >= Q) continue;
-        if (q == Q - 1) {
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                out.B[0][j] = bt[q][0][j] + Mm[q].a * tn[0][j] + Mm[q].b * tn[1][j];
-                out.B[1][j] = bt[q][1][j] + Mm[q].c * tn[0][j] + Mm[q].d * tn[1][j];
-            }
-        }
-        double t[2][5];
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            t[0][j] = tau[q][0][j] + N[q].a * tn[0][j] + N[q].b * tn[1][j];
-            t[1][j] = tau[q][1][j] + N[q].c * tn[0][j] + N[q].d * tn[1][j];
+            const M2 BM = mul(mul(Bl, Mm), N);
+            Mm = {BM.a + Br.a, BM.b + Br.b, BM.c + Br.c, BM.d + Br.d};
         }
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-            tn[0][j] = t[0][j];
-            tn[1][j] = t[1][j];
+            acc[0][j] += P.a * tau[0][j] + P.b * tau[1][j];
+            acc[1][j] += P.c * tau[0][j] + P.d * tau[1][j];
+        }
+        P = mul(P, N);
+    }
+    // T_Q is the outer right pair: the forms r1, r2
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            out.T[i][j] = acc[i][j];
+            out.B[i][j] = bt[i][j];
+        }
+    out.T[0][3] += P.a; out.T[0][4] += P.b; out.T[1][3] += P.c; out.T[1][4] += P.d;
+    out.B[0][3] += Mm.a; out.B[0][4] += Mm.b; out.B[1][3] += Mm.c; out.B[1][4] += Mm.d;
+}
+
+// Numeric version with the outer values known: returns the boundary values of
+// sub-segment w, lo = B_{w-1} (the outer l for w = 0) and hi = T_{w+1} (outer r for the
+// last sub-segment).
+__device__ __forceinline__ void chain_numeric(const double *sB, int lane, int Q, int w, double l1, double l2,
+                                              double r1, double r2, double &lo1, double &lo2, double &hi1,
+                                              double &hi2)
+{
+    double bt0 = 0.0, bt1 = 0.0;
+    M2 Mm = {0, 0, 0, 0};
+    double sbt0 = 0.0, sbt1 = 0.0, stau0 = 0.0, stau1 = 0.0; // bt_{w-1}, tau_w
+    M2 sM = {0, 0, 0, 0}, sN = {0, 0, 0, 0};                 // M_{w-1}, N_w
+    double acc0 = 0.0, acc1 = 0.0;
+    M2 P = {1, 0, 0, 1};
+#pragma unroll
+    for (int q = 0; q < NSUB; ++q) {
+        if (q >= Q) break;
+        Rel S;
+        load_rel(sB, q, lane, S);
+        const M2 Tl = {S.T[0][1], S.T[0][2], S.T[1][1], S.T[1][2]};
+        const M2 Tr = {S.T[0][3], S.T[0][4], S.T[1][3], S.T[1][4]};
+        const M2 Bl = {S.B[0][1], S.B[0][2], S.B[1][1], S.B[1][2]};
+        const M2 Br = {S.B[0][3], S.B[0][4], S.B[1][3], S.B[1][4]};
+        double tau0, tau1;
+        M2 N;
+        if (q == 0) {
+            tau0 = S.T[0][0] + Tl.a * l1 + Tl.b * l2;
+            tau1 = S.T[1][0] + Tl.c * l1 + Tl.d * l2;
+            N = Tr;
+            bt0 = S.B[0][0] + Bl.a * l1 + Bl.b * l2;
+            bt1 = S.B[1][0] + Bl.c * l1 + Bl.d * l2;
+            Mm = Br;
+        } else {
+            if (q == w) { sbt0 = bt0; sbt1 = bt1; sM = Mm; }
+            const M2 K = inv_i_minus(mul(Tl, Mm));
+            const double s0 = S.T[0][0] + Tl.a * bt0 + Tl.b * bt1;
+            const double s1 = S.T[1][0] + Tl.c * bt0 + Tl.d * bt1;
+            tau0 = K.a * s0 + K.b * s1;
+            tau1 = K.c * s0 + K.d * s1;
+            N = mul(K, Tr);
+            const double v0 = bt0 + Mm.a * tau0 + Mm.b * tau1;
+            const double v1 = bt1 + Mm.c * tau0 + Mm.d * tau1;
+            bt0 = S.B[0][0] + Bl.a * v0 + Bl.b * v1;
+            bt1 = S.B[1][0] + Bl.c * v0 + Bl.d * v1;
+            const M2 BM = mul(mul(Bl, Mm), N);
+            Mm = {BM.a + Br.a, BM.b + Br.b, BM.c + Br.c, BM.d + Br.d};
+        }
+        if (q == w) { stau0 = tau0; stau1 = tau1; sN = N; }
+        if (q > w) {
+            acc0 += P.a * tau0 + P.b * tau1;
+            acc1 += P.c * tau0 + P.d * tau1;
+            P = mul(P, N);
         }
     }
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        out.T[0][j] = tn[0][j];
-        out.T[1][j] = tn[1][j];
+    // T_{w+1} (the outer r when w is the last sub-segment)
+    hi1 = acc0 + P.a * r1 + P.b * r2;
+    hi2 = acc1 + P.c * r1 + P.d * r2;
+    if (w == 0) {
+        lo1 = l1;
+        lo2 = l2;
+    } else {
+        const double t0 = stau0 + sN.a * hi1 + sN.b * hi2;
+        const double t1 = stau1 + sN.c * hi1 + sN.d * hi2;
+        lo1 = sbt0 + sM.a * t0 + sM.b * t1;
+        lo2 = sbt1 + sM.c * t0 + sM.d * t1;
     }
 }
 
@@ -289,123 +314,92 @@ __device__ __forceinline__ unsigned wave_or(unsigned v)
 // ------------------------------------------------------------------------------------
 // Tile pass. DIR 0: y sweep (columns), DIR 1: x sweep (rows). SOLVE false: emit the
 // tile's segment relations; SOLVE true: finish the solve with the chained boundaries.
+// y-sweep tiles own LT0 = 62 columns: lanes 0 and 63 carry the neighbouring columns so
+// that the x faces of the residual come from lane shuffles.
 // ------------------------------------------------------------------------------------
-template <int DIR, bool SOLVE, bool P32>
-__global__ void __launch_bounds__(BLOCK) k_pass(PassParams p)
+struct FaceQ {
+    double kA, P, Q, F; // k3 A, k1 (f0'_L Lam + f1'_L Gam)/2 - k1 B/ds, the same with R and +B, flux
+};
+
+template <bool FLUX>
+__device__ __forceinline__ FaceQ face_q(const Cell &L, const Cell &R, bool interior, double ids, double k1,
+                                        double k3)
 {
-    __shared__ double sU[TW * UPITCH];
-    __shared__ double sB[NSUB * NREL * 64];
-    __shared__ double sRed[NSUB][2];
-    __shared__ unsigned sFlag[NSUB];
-    static_assert(NSUB * NREL * 64 >= TILE * WPITCH, "second LDS region too small");
+    FaceQ f;
+    const double A = 0.5 * (L.f0 + R.f0), B = 0.5 * (L.f1 + R.f1);
+    const double Lam = (R.lap - L.lap) * ids, Gam = (R.u - L.u) * ids;
+    const double Bi = B * ids;
+    f.kA = interior ? k3 * A : 0.0;
+    f.P = interior ? k1 * (L.f0p * Lam + L.f1p * Gam - Bi) : 0.0;
+    f.Q = interior ? k1 * (R.f0p * Lam + R.f1p * Gam + Bi) : 0.0;
+    f.F = (FLUX && interior) ? A * Lam + B * Gam : 0.0;
+    return f;
+}
 
-    const int nx = p.nx, ny = p.ny;
-    const int ntiles = p.tiles_x * p.tiles_y;
-    const int t = xcd_tile(blockIdx.x, ntiles);
-    const int tx = t % p.tiles_x, ty = t / p.tiles_x;
-    const int x0 = seg_start(tx, nx), x1 = seg_start(tx + 1, nx);
-    const int y0 = seg_start(ty, ny), y1 = seg_start(ty + 1, ny);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    if (p.res_clear != nullptr && blockIdx.x == 0 && tid < RES_WORDS) p.res_clear[tid] = 0ull;
-
-    for (int idx = tid; idx < TW * TW; idx += BLOCK) {
-        const int ly = idx / TW, lx = idx - ly * TW;
-        const int gx = crefl(x0 - HALO + lx, nx), gy = crefl(y0 - HALO + ly, ny);
-        sU[ly * UPITCH + lx] = p.u[(size_t)gy * nx + gx];
-    }
-    for (int idx = tid; idx < TILE * TILE; idx += BLOCK) {
-        const int ly = idx >> 6, lx = idx & 63;
-        const int gx = min(x0 + lx, nx - 1), gy = min(y0 + ly, ny - 1);
-        sB[ly * WPITCH + lx] = p.in2[(size_t)gy * nx + gx];
-    }
-    __syncthreads();
-
-    const int lbase = DIR == 0 ? x0 : y0;
-    const int nlt = DIR == 0 ? x1 - x0 : y1 - y0;   // lines in this tile
-    const int pbase = DIR == 0 ? y0 : x0;
-    const int npos = DIR == 0 ? y1 - y0 : x1 - x0;  // segment length
-    const int Nl = DIR == 0 ? nx : ny;
-    const int Np = DIR == 0 ? ny : nx;
-    const int qseg = DIR == 0 ? ty : tx;
-    const int gl = lbase + lane;
-    const bool active = lane < nlt;
-    const int nsub = min(NSUB, npos / 2);
-    const int ps = (wave * npos) / nsub;
-    const int len = wave < nsub ? ((wave + 1) * npos) / nsub - ps : 0;
+// Elimination sweep of one wave over its sub-segment [ps, ps+len) for all 64 lanes:
+// assembles, per position, the cell coefficients, the residual (y sweep) and the five
+// bands of I + c J, and runs the LU step with the sub-segment's outer unknowns kept
+// symbolic. FAST: interior tile with 16 positions per wave, no domain boundary inside
+// (no folded ghost columns, no zero-flux faces, no per-lane boundary selects).
+template <int DIR, bool SOLVE, bool P32, bool FAST>
+__device__ __forceinline__ void sweep(const double *sU, const double *sB, const PassParams &p, int lane, int ps,
+                                      int len, int pbase, int Np, int gl, int Nl, bool owned, double *fa,
+                                      double *fb, double *fz, double *fph, double *fps, Rel &mine,
+                                      double &rmax, unsigned &flags)
+{
     const double ids = p.ids, ids2 = p.ids2, k1 = p.k1, k3 = p.k3;
-
-    double fa[SUB], fb[SUB], fz[SUB], fph[SUB], fps[SUB], fu[SUB];
-    Rel mine;
-    double rmax = 0.0;
-    unsigned flags = 0;
-
-    if (len > 0) {
-        Cell cm = cell_at<DIR, P32>(sU, p.M, ids2, lane, ps - 1);
+    {
+        const Cell cm = cell_at<DIR, P32>(sU, p.M, ids2, lane, ps - 1);
         Cell c0 = cell_at<DIR, P32>(sU, p.M, ids2, lane, ps);
+        FaceQ fm = face_q<DIR == 0>(cm, c0, FAST || pbase + ps > 0, ids, k1, k3);
         double al1 = 0.0, be1 = 0.0, al2 = 0.0, be2 = 0.0;
         // rows s-2 and s-1 stand for the outer unknowns l1 and l2
         double z1 = 0.0, ph1 = 0.0, ps1 = 1.0, z2 = 0.0, ph2 = 1.0, ps2 = 0.0;
         double g1 = 0.0, g2 = 0.0, h1 = 0.0, h2 = 0.0;
         double sgz = 0.0, sgph = 0.0, sgps = 0.0, shz = 0.0, shph = 0.0, shps = 0.0;
-#pragma unroll
+        // the solve pass keeps per-position factors in registers (full unroll); the
+        // relations pass needs none and, off the interior path, is only partly unrolled
+        constexpr int UNR = SOLVE ? SUB : (FAST ? (DIR == 0 ? K1Y_FAST_UNROLL : SUB) : K1_UNROLL);
+#pragma unroll UNR
         for (int k = 0; k < SUB; ++k) {
-            if (k < len) {
+            if (FAST || k < len) {
                 const int lp = ps + k;
-                const int gp = pbase + lp;
+                const int gp = pbase + lp;          // wave-uniform
                 const Cell cp = cell_at<DIR, P32>(sU, p.M, ids2, lane, lp + 1);
-                const bool fm = gp > 0, fpl = gp < Np - 1;
-                // faces lp-1/2 (m) and lp+1/2 (p) along the line: mean coefficients,
-                // full-Laplacian and value differences
-                const double Am = 0.5 * (cm.f0 + c0.f0), Bm = 0.5 * (cm.f1 + c0.f1);
-                const double Ap = 0.5 * (c0.f0 + cp.f0), Bp = 0.5 * (c0.f1 + cp.f1);
-                const double Lm = (c0.lap - cm.lap) * ids, Gm = (c0.u - cm.u) * ids;
-                const double Lp = (cp.lap - c0.lap) * ids, Gp = (cp.u - c0.u) * ids;
+                const FaceQ fp = face_q<DIR == 0>(c0, cp, FAST || gp < Np - 1, ids, k1, k3);
                 double rhs;
                 if (DIR == 0) {
-                    // residual -G(u_k) = -(u_k - b^n + theta dt D(u_k)); D uses the x
-                    // faces of this cell too
-                    const Cell aw = cell_at<DIR, P32>(sU, p.M, ids2, lane - 1, lp);
-                    const Cell ae = cell_at<DIR, P32>(sU, p.M, ids2, lane + 1, lp);
-                    const double Fw = gl > 0 ? 0.5 * (aw.f0 + c0.f0) * ((c0.lap - aw.lap) * ids)
-                                                   + 0.5 * (aw.f1 + c0.f1) * ((c0.u - aw.u) * ids)
-                                             : 0.0;
-                    const double Fe = gl < Nl - 1 ? 0.5 * (c0.f0 + ae.f0) * ((ae.lap - c0.lap) * ids)
-                                                        + 0.5 * (c0.f1 + ae.f1) * ((ae.u - c0.u) * ids)
-                                                  : 0.0;
-                    const double Fs = fm ? Am * Lm + Bm * Gm : 0.0;
-                    const double Fn = fpl ? Ap * Lp + Bp * Gp : 0.0;
-                    const double D = (Fe - Fw + Fn - Fs) * ids;
+                    // -G(u_k) = -(u_k - b^n + theta dt D(u_k)); the x faces of this cell
+                    // use the neighbouring lanes' cell values
+                    const double eu = __shfl_down(c0.u, 1), el = __shfl_down(c0.lap, 1);
+                    const double e0 = __shfl_down(c0.f0, 1), e1 = __shfl_down(c0.f1, 1);
+                    const double Fe0 = 0.5 * (c0.f0 + e0) * ((el - c0.lap) * ids) + 0.5 * (c0.f1 + e1) * ((eu - c0.u) * ids);
+                    const double Fe = (FAST || gl < Nl - 1) ? Fe0 : 0.0;
+                    const double Fwr = __shfl_up(Fe, 1);
+                    const double Fw = (FAST || gl > 0) ? Fwr : 0.0;
+                    const double D = (Fe - Fw + fp.F - fm.F) * ids;
                     const double G = c0.u - sB[lp * WPITCH + lane] + p.cD * D;
                     rhs = -G;
-                    if (active && !SOLVE) {
+                    if (!SOLVE && owned) {
                         rmax = fmax(rmax, fabs(G));
                         if (G != G) flags |= FLAG_NAN;
                     }
                 } else {
                     rhs = sB[lane * WPITCH + lp];
                 }
-                // bands of I + c J along the line (split Jacobian of the face fluxes)
-                double a = 0.0, b = 0.0, c = 1.0, d = 0.0, e = 0.0;
-                if (fpl) {
-                    const double kA = k3 * Ap;
-                    b -= kA;
-                    c += 3.0 * kA + k1 * (0.5 * c0.f0p * Lp + 0.5 * c0.f1p * Gp - Bp * ids);
-                    d += -3.0 * kA + k1 * (0.5 * cp.f0p * Lp + 0.5 * cp.f1p * Gp + Bp * ids);
-                    e += kA;
+                // bands of I + c J along the line from the two face records
+                double a = fm.kA;
+                double b = -fp.kA - 3.0 * fm.kA - fm.P;
+                double c = 1.0 + 3.0 * fp.kA + fp.P + 3.0 * fm.kA - fm.Q;
+                double d = -3.0 * fp.kA + fp.Q - fm.kA;
+                double e = fp.kA;
+                if (!FAST) {
+                    // fold ghost columns back (even reflection of the perturbation)
+                    if (gp == 0) { c += b; d += a; b = 0.0; a = 0.0; }
+                    else if (gp == 1) { b += a; a = 0.0; }
+                    if (gp == Np - 1) { c += d; b += e; d = 0.0; e = 0.0; }
+                    else if (gp == Np - 2) { d += e; e = 0.0; }
                 }
-                if (fm) {
-                    const double kA = k3 * Am;
-                    a += kA;
-                    b += -3.0 * kA - k1 * (0.5 * cm.f0p * Lm + 0.5 * cm.f1p * Gm - Bm * ids);
-                    c += 3.0 * kA - k1 * (0.5 * c0.f0p * Lm + 0.5 * c0.f1p * Gm + Bm * ids);
-                    d -= kA;
-                }
-                // fold ghost columns back (even reflection of the perturbation)
-                if (gp == 0) { c += b; d += a; b = 0.0; a = 0.0; }
-                else if (gp == 1) { b += a; a = 0.0; }
-                if (gp == Np - 1) { c += d; b += e; d = 0.0; e = 0.0; }
-                else if (gp == Np - 2) { d += e; e = 0.0; }
                 // LU elimination step; the right-hand side carries the symbolic outer
                 // unknowns (z: constant part, ph: coefficient of l1, ps: of l2)
                 const double gam = b - a * al2;
@@ -422,13 +416,13 @@ __global__ void __launch_bounds__(BLOCK) k_pass(PassParams p)
                 sgz += g * z; sgph += g * ph; sgps += g * pss;
                 shz += h * z; shph += h * ph; shps += h * pss;
                 if (SOLVE) {
-                    fa[k] = al; fb[k] = be; fz[k] = z; fph[k] = ph; fps[k] = pss; fu[k] = c0.u;
+                    fa[k] = al; fb[k] = be; fz[k] = z; fph[k] = ph; fps[k] = pss;
                 }
                 g2 = g1; g1 = g; h2 = h1; h1 = h;
                 al2 = al1; be2 = be1; al1 = al; be1 = be;
                 z2 = z1; ph2 = ph1; ps2 = ps1; z1 = z; ph1 = ph; ps1 = pss;
-                cm = c0;
                 c0 = cp;
+                fm = fp;
             }
         }
         // bottom pair: x_{e-1} = Z_{e-1} - al1 r1 - be1 r2, x_{e-2} = Z_{e-2} - be2 r1 - al2 x_{e-1}
@@ -441,11 +435,99 @@ __global__ void __launch_bounds__(BLOCK) k_pass(PassParams p)
         mine.T[1][0] = shz; mine.T[1][1] = shph; mine.T[1][2] = shps;
         mine.T[1][3] = -h2 * be2 - h1 * al1; mine.T[1][4] = -h1 * be1;
     }
+}
+
+template <int DIR, bool SOLVE, bool P32>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SOLVE ? K3_WAVES_PER_EU : 2, SOLVE ? K3_WAVES_PER_EU : 2))) k_pass(PassParams p)
+{
+    __shared__ double sU[TW * UPITCH];
+    __shared__ double sB[NSUB * NREL * 64];
+    __shared__ double sRed[NSUB];
+    __shared__ unsigned sFlag[NSUB];
+    static_assert(NSUB * NREL * 64 >= TILE * WPITCH, "second LDS region too small");
+
+    const int nx = p.nx, ny = p.ny;
+    const int ntiles = p.tiles_x * p.tiles_y;
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const int tx = t % p.tiles_x, ty = t / p.tiles_x;
+    int x0, x1, y0, y1;
+    if (DIR == 0) {
+        x0 = tx * LT0; x1 = min(x0 + LT0, nx);
+        y0 = seg_start(ty, ny); y1 = seg_start(ty + 1, ny);
+    } else {
+        x0 = seg_start(tx, nx); x1 = seg_start(tx + 1, nx);
+        y0 = ty * TILE; y1 = min(y0 + TILE, ny);
+    }
+    const int bxo = DIR == 0 ? x0 - 1 : x0;  // grid x of lane/position 0 of the tile
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    if (p.res_clear != nullptr && blockIdx.x == 0 && tid < RES_WORDS) p.res_clear[tid] = 0ull;
+
+    {
+        // issue every global load of the tile before the first LDS store
+        constexpr int NU = (TW * TW + BLOCK - 1) / BLOCK, NB = TILE * TILE / BLOCK;
+        double vu[NU], vb[NB];
+#pragma unroll
+        for (int r = 0; r < NU; ++r) {
+            const int idx = tid + r * BLOCK;
+            const int ly = min(idx / TW, TW - 1), lx = idx - (idx / TW) * TW;
+            const int gx = crefl(bxo - HALO + lx, nx), gy = crefl(y0 - HALO + ly, ny);
+            vu[r] = idx < TW * TW ? p.u[(size_t)gy * nx + gx] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            const int idx = tid + r * BLOCK;
+            const int ly = idx >> 6, lx = idx & 63;
+            const int gx = crefl(bxo + lx, nx), gy = min(y0 + ly, ny - 1);
+            vb[r] = p.in2[(size_t)gy * nx + gx];
+        }
+#pragma unroll
+        for (int r = 0; r < NU; ++r) {
+            const int idx = tid + r * BLOCK;
+            const int ly = idx / TW, lx = idx - ly * TW;
+            if (idx < TW * TW) sU[ly * UPITCH + lx] = vu[r];
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            const int idx = tid + r * BLOCK;
+            sB[(idx >> 6) * WPITCH + (idx & 63)] = vb[r];
+        }
+    }
+    __syncthreads();
+
+    const int lane0 = DIR == 0 ? 1 : 0;                 // first lane that owns a line
+    const int nlt = DIR == 0 ? x1 - x0 : y1 - y0;       // lines owned by the tile
+    const bool owned = lane >= lane0 && lane < lane0 + nlt;
+    const int gl = (DIR == 0 ? x0 - 1 : y0) + lane;     // grid line of this lane
+    const int pbase = DIR == 0 ? y0 : x0;
+    const int npos = DIR == 0 ? y1 - y0 : x1 - x0;      // segment length
+    const int Nl = DIR == 0 ? nx : ny;
+    const int Np = DIR == 0 ? ny : nx;
+    const int qseg = DIR == 0 ? ty : tx;
+    const int nsub = min(NSUB, npos / 2);
+    const int ps = (wave * npos) / nsub;
+    const int len = wave < nsub ? ((wave + 1) * npos) / nsub - ps : 0;
+    double fa[SUB], fb[SUB], fz[SUB], fph[SUB], fps[SUB];
+    Rel mine;
+    double rmax = 0.0;
+    unsigned flags = 0;
+
+    // interior tiles take the specialised path (wave-uniform branch)
+    const bool fast = npos == TILE && pbase >= 2 && pbase + TILE <= Np - 2
+                      && (DIR == 1 || (x0 > 0 && x0 + LT0 < nx && nlt == LT0));
+    if (len > 0) {
+        if (fast)
+            sweep<DIR, SOLVE, P32, true>(sU, sB, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph, fps,
+                                         mine, rmax, flags);
+        else
+            sweep<DIR, SOLVE, P32, false>(sU, sB, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph, fps,
+                                          mine, rmax, flags);
+    }
 
     if (!SOLVE && DIR == 0 && p.res != nullptr) {
         const double wm = wave_max(rmax);
         const unsigned wf = wave_or(flags);
-        if (lane == 0) { sRed[wave][0] = wm; sFlag[wave] = wf; }
+        if (lane == 0) { sRed[wave] = wm; sFlag[wave] = wf; }
     }
     __syncthreads(); // all sweeps done: sB may be reused for the relation exchange
     if (len > 0) {
@@ -464,26 +546,13 @@ __global__ void __launch_bounds__(BLOCK) k_pass(PassParams p)
         if (DIR == 0 && p.res != nullptr && tid == 0) {
             double m = 0.0;
             unsigned f = 0;
-            for (int w = 0; w < NSUB; ++w) { m = fmax(m, sRed[w][0]); f |= sFlag[w]; }
+            for (int w = 0; w < NSUB; ++w) { m = fmax(m, sRed[w]); f |= sFlag[w]; }
             atomicMax(&p.res[RES_RMAX], (unsigned long long)__double_as_longlong(m));
             if (f) atomicOr(&p.res[RES_FLAGS], (unsigned long long)f);
         }
-        if (wave == 0 && active) {
-            Rel R[NSUB];
-#pragma unroll
-            for (int q = 0; q < NSUB; ++q) {
-                if (q >= nsub) break;
-                const double *src = sB + (size_t)q * NREL * 64 + lane;
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 5; ++j) {
-                        R[q].T[i][j] = src[(i * 5 + j) * 64];
-                        R[q].B[i][j] = src[(10 + i * 5 + j) * 64];
-                    }
-            }
+        if (wave == 0 && owned) {
             Rel seg;
-            chain_symbolic<NSUB>(R, nsub, seg);
+            chain_symbolic(sB, lane, nsub, seg);
             double *o = p.rel + (size_t)qseg * NREL * Nl + gl;
 #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -497,76 +566,59 @@ __global__ void __launch_bounds__(BLOCK) k_pass(PassParams p)
     }
 
     // ---- SOLVE: boundary values of this wave's sub-segment, then back-substitution
-    double xs[SUB];
-    double emax = 0.0;
+    double wl1 = 0.0, wl2 = 0.0, xr1 = 0.0, xr2 = 0.0;
     if (len > 0) {
-        Rel R[NSUB];
-#pragma unroll
-        for (int q = 0; q < NSUB; ++q) {
-            if (q >= nsub) break;
-            const double *src = sB + (size_t)q * NREL * 64 + lane;
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 5; ++j) {
-                    R[q].T[i][j] = src[(i * 5 + j) * 64];
-                    R[q].B[i][j] = src[(10 + i * 5 + j) * 64];
-                }
-        }
-        const double *ex = p.ext + (size_t)qseg * NEXT * Nl + min(gl, Nl - 1);
+        const double *ex = p.ext + (size_t)qseg * NEXT * Nl + min(max(gl, 0), Nl - 1);
         const double l1 = ex[0], l2 = ex[(size_t)Nl], r1 = ex[(size_t)2 * Nl], r2 = ex[(size_t)3 * Nl];
-        double lo[NSUB][2], hi[NSUB][2];
-        chain_numeric<NSUB>(R, nsub, l1, l2, r1, r2, lo, hi);
-        double wl1 = lo[0][0], wl2 = lo[0][1], x1 = hi[0][0], x2 = hi[0][1];
-#pragma unroll
-        for (int q = 1; q < NSUB; ++q)
-            if (q == wave) { wl1 = lo[q][0]; wl2 = lo[q][1]; x1 = hi[q][0]; x2 = hi[q][1]; }
-#pragma unroll
-        for (int k = SUB - 1; k >= 0; --k) {
-            if (k < len) {
-                const double x = fz[k] + fph[k] * wl1 + fps[k] * wl2 - fa[k] * x1 - fb[k] * x2;
-                xs[k] = x;
-                x2 = x1;
-                x1 = x;
-            }
-        }
+        chain_numeric(sB, lane, nsub, wave, l1, l2, r1, r2, wl1, wl2, xr1, xr2);
     }
-    __syncthreads(); // relation records consumed: sU becomes the output staging tile
 
     if (DIR == 0) {
-        // w is stored straight from registers: lanes cover consecutive x
-        if (len > 0 && active) {
+        // w goes straight from registers to memory: lanes cover consecutive x
+        if (len > 0) {
 #pragma unroll
-            for (int k = 0; k < SUB; ++k)
-                if (k < len) p.out[(size_t)(pbase + ps + k) * nx + gl] = xs[k];
+            for (int k = SUB - 1; k >= 0; --k) {
+                if (k < len) {
+                    const double x = fz[k] + fph[k] * wl1 + fps[k] * wl2 - fa[k] * xr1 - fb[k] * xr2;
+                    if (owned) p.out[(size_t)(pbase + ps + k) * nx + gl] = x;
+                    xr2 = xr1;
+                    xr1 = x;
+                }
+            }
         }
         return;
     } else {
-        if (len > 0 && active) {
+        __syncthreads(); // relation records consumed: sB becomes the output staging tile
+        double emax = 0.0;
+        if (len > 0) {
 #pragma unroll
-            for (int k = 0; k < SUB; ++k) {
+            for (int k = SUB - 1; k >= 0; --k) {
                 if (k < len) {
-                    const double v = xs[k];
-                    const double un = fu[k] + v;
-                    const double q = fabs(v) * rcp(fabs(fu[k]));
-                    emax = fmax(emax, q);
-                    if (!(un > 0.0)) flags |= (un != un || v != v) ? FLAG_NAN : FLAG_NONPOS;
-                    sU[lane * UPITCH + ps + k] = un;
+                    const double v = fz[k] + fph[k] * wl1 + fps[k] * wl2 - fa[k] * xr1 - fb[k] * xr2;
+                    xr2 = xr1;
+                    xr1 = v;
+                    const double uk = uat<DIR>(sU, lane, ps + k);
+                    const double un = uk + v;
+                    if (owned) {
+                        emax = fmax(emax, fabs(v) * rcp(fabs(uk)));
+                        if (!(un > 0.0)) flags |= (un != un || v != v) ? FLAG_NAN : FLAG_NONPOS;
+                    }
+                    sB[lane * WPITCH + ps + k] = un;
                 }
             }
         }
         const double wm = wave_max(emax);
         const unsigned wf = wave_or(flags);
-        if (lane == 0) { sRed[wave][0] = wm; sFlag[wave] = wf; }
+        if (lane == 0) { sRed[wave] = wm; sFlag[wave] = wf; }
         __syncthreads();
         for (int idx = tid; idx < TILE * TILE; idx += BLOCK) {
             const int ly = idx >> 6, lx = idx & 63;
-            if (ly < nlt && lx < npos) p.out[(size_t)(y0 + ly) * nx + x0 + lx] = sU[ly * UPITCH + lx];
+            if (ly < nlt && lx < npos) p.out[(size_t)(y0 + ly) * nx + x0 + lx] = sB[ly * WPITCH + lx];
         }
         if (tid == 0 && p.res != nullptr) {
             double m = 0.0;
             unsigned f = 0;
-            for (int w = 0; w < NSUB; ++w) { m = fmax(m, sRed[w][0]); f |= sFlag[w]; }
+            for (int w = 0; w < NSUB; ++w) { m = fmax(m, sRed[w]); f |= sFlag[w]; }
             atomicMax(&p.res[RES_EMAX], (unsigned long long)__double_as_longlong(m));
             if (f) atomicOr(&p.res[RES_FLAGS], (unsigned long long)f);
         }
@@ -578,23 +630,32 @@ __global__ void __launch_bounds__(BLOCK) k_pass(PassParams p)
 // values are zero at the two ends of the line), then back-substitution giving every
 // segment its two left and two right neighbouring values.
 // ------------------------------------------------------------------------------------
+__device__ __forceinline__ void load_rec(const double *r, size_t NL, double (&T)[2][5], double (&B)[2][5])
+{
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            T[i][j] = r[(size_t)(i * 5 + j) * NL];
+            B[i][j] = r[(size_t)(10 + i * 5 + j) * NL];
+        }
+}
+
 __global__ void __launch_bounds__(64) k_chain(ChainParams c)
 {
     const int line = blockIdx.x * 64 + threadIdx.x;
     if (line >= c.nlines) return;
     const size_t NL = (size_t)c.nlines;
+    const size_t RS = (size_t)NREL * NL; // stride between segment records
     double tau0 = 0.0, tau1 = 0.0, bt0 = 0.0, bt1 = 0.0;
     M2 N = {0, 0, 0, 0}, Mm = {0, 0, 0, 0};
+    // records are loaded two segments ahead of their use to hide memory latency
+    double T[2][5], B[2][5], Tn[2][5], Bn[2][5], Tnn[2][5], Bnn[2][5];
+    const double *base = c.rel + line;
+    load_rec(base, NL, T, B);
+    if (c.P > 1) load_rec(base + RS, NL, Tn, Bn);
     for (int q = 0; q < c.P; ++q) {
-        const double *r = c.rel + (size_t)q * NREL * NL + line;
-        double T[2][5], B[2][5];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                T[i][j] = r[(size_t)(i * 5 + j) * NL];
-                B[i][j] = r[(size_t)(10 + i * 5 + j) * NL];
-            }
+        if (q + 2 < c.P) load_rec(base + (size_t)(q + 2) * RS, NL, Tnn, Bnn);
         const M2 Tl = {T[0][1], T[0][2], T[1][1], T[1][2]};
         const M2 Tr = {T[0][3], T[0][4], T[1][3], T[1][4]};
         const M2 Bl = {B[0][1], B[0][2], B[1][1], B[1][2]};
@@ -620,25 +681,48 @@ __global__ void __launch_bounds__(64) k_chain(ChainParams c)
         w[0] = tau0; w[NL] = tau1; w[2 * NL] = N.a; w[3 * NL] = N.b; w[4 * NL] = N.c; w[5 * NL] = N.d;
         w[6 * NL] = bt0; w[7 * NL] = bt1; w[8 * NL] = Mm.a; w[9 * NL] = Mm.b; w[10 * NL] = Mm.c;
         w[11 * NL] = Mm.d;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                T[i][j] = Tn[i][j]; B[i][j] = Bn[i][j];
+                Tn[i][j] = Tnn[i][j]; Bn[i][j] = Bnn[i][j];
+            }
     }
+    // backward substitution; the chain records of segments q and q-1 are read ahead
     double tn0 = 0.0, tn1 = 0.0;
+    const double *cb = c.chain + line;
+    const size_t CS = (size_t)NCHAIN * NL;
+    double cq[6], cp[6], cpp[6]; // (tau0, tau1, N) of q; (bt0, bt1, M) of q-1
+    auto ld_t = [&](int q, double *o) {
+        const double *w = cb + (size_t)q * CS;
+        for (int k = 0; k < 6; ++k) o[k] = w[(size_t)k * NL];
+    };
+    auto ld_b = [&](int q, double *o) {
+        const double *w = cb + (size_t)q * CS + 6 * NL;
+        for (int k = 0; k < 6; ++k) o[k] = w[(size_t)k * NL];
+    };
+    ld_t(c.P - 1, cq);
+    if (c.P > 1) ld_b(c.P - 2, cp);
     for (int q = c.P - 1; q >= 0; --q) {
-        const double *w = c.chain + (size_t)q * NCHAIN * NL + line;
-        const double t0 = w[0] + w[2 * NL] * tn0 + w[3 * NL] * tn1;
-        const double t1 = w[NL] + w[4 * NL] * tn0 + w[5 * NL] * tn1;
+        double nq[6] = {0, 0, 0, 0, 0, 0};
+        if (q > 0) ld_t(q - 1, nq);
+        if (q > 1) ld_b(q - 2, cpp);
+        const double t0 = cq[0] + cq[2] * tn0 + cq[3] * tn1;
+        const double t1 = cq[1] + cq[4] * tn0 + cq[5] * tn1;
         double *e = c.ext + (size_t)q * NEXT * NL + line;
         e[2 * NL] = tn0;
         e[3 * NL] = tn1;
         if (q > 0) {
-            const double *v = c.chain + (size_t)(q - 1) * NCHAIN * NL + line;
-            e[0] = v[6 * NL] + v[8 * NL] * t0 + v[9 * NL] * t1;
-            e[NL] = v[7 * NL] + v[10 * NL] * t0 + v[11 * NL] * t1;
+            e[0] = cp[0] + cp[2] * t0 + cp[3] * t1;
+            e[NL] = cp[1] + cp[4] * t0 + cp[5] * t1;
         } else {
             e[0] = 0.0;
             e[NL] = 0.0;
         }
         tn0 = t0;
         tn1 = t1;
+        for (int k = 0; k < 6; ++k) { cq[k] = nq[k]; cp[k] = cpp[k]; }
     }
 }
 
