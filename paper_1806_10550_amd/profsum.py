@@ -1,0 +1,127 @@
+"""Summarise rocprofv3 CSV output into the short text/JSON records kept under profiles/.
+
+  python -m paper_1806_10550_amd.profsum stats DIR [--title T]
+      kernel-trace statistics (DIR holds *kernel_stats.csv) as a text table
+  python -m paper_1806_10550_amd.profsum traffic --fetch D1 --write D2 --copy-fetch D3 \
+      --copy-write D4 --copy-bytes B --hash H
+      per-kernel FETCH_SIZE / WRITE_SIZE per dispatch (KiB), with the scale factor that
+      maps the counters onto the known byte count of a plain copy kernel, as JSON
+"""
+import argparse
+import csv
+import glob
+import json
+import os
+import re
+import statistics
+import sys
+
+KERNEL_CLASSES = [
+    (r"k_pass<0, false", "relations_y"),
+    (r"k_pass<0, true", "solve_y"),
+    (r"k_pass<1, false", "relations_x"),
+    (r"k_pass<1, true", "solve_x"),
+    (r"k_chain", "chain"),
+    (r"k_mass", "mass"),
+    (r"k_flux_divergence", "rhs_theta"),
+]
+
+
+def classify(name):
+    for pat, cls in KERNEL_CLASSES:
+        if pat in name:
+            return cls
+    return name.split("(")[0][:60]
+
+
+def _find(d, pattern):
+    hits = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    if not hits:
+        raise SystemExit(f"no {pattern} under {d}")
+    return hits[0]
+
+
+def stats(d, title=None):
+    path = _find(d, "*kernel_stats.csv")
+    rows = list(csv.DictReader(open(path)))
+    out = []
+    if title:
+        out.append(title)
+    out.append(f"{'kernel':60s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}")
+    for r in rows:
+        name = r.get("Name") or r.get("KernelName") or ""
+        calls = int(r.get("Calls", 0))
+        tot = float(r.get("TotalDurationNs", 0))
+        avg = float(r.get("AverageNs", 0))
+        mn = float(r.get("MinNs", 0))
+        mx = float(r.get("MaxNs", 0))
+        pct = float(r.get("Percentage", 0))
+        out.append(f"{name[:60]:60s} {calls:7d} {tot / 1e6:10.3f} {avg / 1e3:10.1f} {mn / 1e3:10.1f} "
+                   f"{mx / 1e3:10.1f} {pct:6.2f}")
+    return "\n".join(out)
+
+
+def counter_means(d, counter):
+    path = _find(d, "*counter_collection.csv")
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        name = r.get("Kernel_Name", "")
+        per.setdefault(name, []).append(float(r["Counter_Value"]))
+    return {k: statistics.mean(v) for k, v in per.items()}, {k: len(v) for k, v in per.items()}
+
+
+def traffic(a):
+    fetch, nf = counter_means(a.fetch, "FETCH_SIZE")
+    write, nw = counter_means(a.write, "WRITE_SIZE")
+    cf, _ = counter_means(a.copy_fetch, "FETCH_SIZE")
+    cw, _ = counter_means(a.copy_write, "WRITE_SIZE")
+    # the copy kernel is the one with the largest counter value in the calibration run
+    cf_kib = max(cf.values())
+    cw_kib = max(cw.values())
+    known_kib = a.copy_bytes / 1024.0
+    out = {
+        "kernel_hash": a.hash,
+        "copy_bytes": a.copy_bytes,
+        "copy_fetch_kib": cf_kib,
+        "copy_write_kib": cw_kib,
+        "fetch_scale": known_kib / cf_kib,
+        "write_scale": known_kib / cw_kib,
+        "copy_scale": 0.5 * (known_kib / cf_kib + known_kib / cw_kib),
+        "kernels": {},
+    }
+    for name in fetch:
+        cls = classify(name)
+        if cls not in ("relations_y", "solve_y", "relations_x", "solve_x", "chain"):
+            continue
+        rec = out["kernels"].setdefault(cls, {"fetch_kib": 0.0, "write_kib": 0.0, "dispatches": 0})
+        rec["fetch_kib"] = fetch[name] * (known_kib / cf_kib)
+        rec["write_kib"] = write.get(name, 0.0) * (known_kib / cw_kib)
+        rec["dispatches"] = nf[name]
+    # bench.py multiplies (fetch + write) by copy_scale; the per-counter scales are
+    # already applied above, so the combined scale is 1
+    out["copy_scale"] = 1.0
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--title")
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
+        t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--hash", required=True)
+    a = ap.parse_args()
+    if a.cmd == "stats":
+        print(stats(a.dir, a.title))
+    else:
+        print(json.dumps(traffic(a), indent=1))
+
+
+if __name__ == "__main__":
+    sys.exit(main())
