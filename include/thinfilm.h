@@ -123,6 +123,37 @@ tf_status tf_profile(tf_grid *g, int on);
 int tf_profile_read(tf_grid *g, double *ms, long *count, int n);
 const char *tf_profile_names(void);
 
+/* ---- Ensembles ---------------------------------------------------------------------
+ * Many independent films (different sizes, kappa and ds; common b, n, m) advanced in
+ * lockstep: one Newton iteration of every film that is still iterating is one replay of
+ * a captured HIP graph; each film's Newton / dt control (Fig. FlowChartTime) runs on the
+ * device, so converged films drop out while the others continue. Backward Euler only.
+ * The films' states live in ONE packed device buffer: film f occupies nx[f]*ny[f]
+ * row-major doubles starting at offsets[f] (tf_ensemble_offsets), films back to back in
+ * the order given. Work is done on an internal stream ordered after `stream`. */
+typedef struct tf_ensemble tf_ensemble;
+tf_status tf_ensemble_create(int nfilms, const int *nx, const int *ny, const double *ds, const double *kappa,
+                             double b, double n, double m, void *stream, tf_ensemble **out);
+tf_status tf_ensemble_destroy(tf_ensemble *e);
+/* scheme as for tf_set_scheme; theta must be 1 (TF_EINVAL otherwise) */
+tf_status tf_ensemble_set_scheme(tf_ensemble *e, const tf_scheme *s);
+/* total number of cells (length of the packed buffer) */
+long long tf_ensemble_size(const tf_ensemble *e);
+/* host array of nfilms offsets (in doubles) of each film in the packed buffer */
+tf_status tf_ensemble_offsets(const tf_ensemble *e, long long *offsets);
+/* Borrow the packed state (device, tf_ensemble_size doubles); films holding h <= 0 or
+ * NaN are marked TF_ENONPOS and never stepped. Resets every film's time and status. */
+tf_status tf_ensemble_bind(tf_ensemble *e, double *packed_dev);
+/* Advance every film by nsteps accepted steps. dt_per_film (host, nfilms): dt to try in,
+ * next dt out. status_per_film (host, nullable): TF_OK, TF_ENOCONV or TF_ENONPOS per film
+ * (a failed film keeps its last accepted state and stops). iters_per_film (host,
+ * nullable): Newton iterations of each film in this call. Returns TF_OK when every film
+ * succeeded, else the first failing film's status. */
+tf_status tf_ensemble_step(tf_ensemble *e, int nsteps, double *dt_per_film, int *status_per_film,
+                           int *iters_per_film);
+/* Record of film `film` after the last tf_ensemble_step (time, last dt, iterations). */
+tf_status tf_ensemble_film_info(const tf_ensemble *e, int film, tf_step_info *info);
+
 /* Description of the calling thread's most recent error (never NULL). */
 const char *tf_last_error(void);
 

@@ -41,6 +41,10 @@ constexpr int RES_SLOTS = 4;
 
 } // namespace
 
+namespace tf_detail {
+void set_error(const std::string &msg) { g_err = msg; }
+} // namespace tf_detail
+
 struct tf_grid {
     int nx = 0, ny = 0;
     double ds = 0.0;

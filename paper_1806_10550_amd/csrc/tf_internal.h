@@ -74,6 +74,37 @@ struct ChainParams {
 };
 
 enum ResultWord { RES_EMAX = 0, RES_RMAX = 1, RES_FLAGS = 2, RES_WORDS = 8 };
+
+// ---- ensemble of films packed in one buffer --------------------------------------------
+struct FilmDesc {          // constant per film
+    int nx, ny, Px, Py;
+    double ds;
+    Model M;
+    long long off;         // first cell of the film in the packed field buffers
+    long long roff;        // first (segment, line) record of the film in the interface scratch
+};
+
+struct FilmState {         // per-film Newton / time-step state, updated on the device
+    double dt, t, dt_used, e_last, r_last;
+    int k, cur, it, nxt;   // iteration in the attempt; buffer index of u^n, u_k, u_{k+1} (0,1,2)
+    int active, status, successes, rejections, newton, total;
+    unsigned long long red[4]; // reduction words of the current iteration (RES_EMAX..)
+};
+
+struct EnsScheme {
+    double theta, tol, dt_min, dt_max, dt_shrink, dt_grow;
+    int max_newton, grow_after, adaptive;
+};
+
+struct EnsParams {
+    const FilmDesc *desc;
+    FilmState *state;
+    const int *items;      // tiles: (film, tx, ty); chain blocks: (film, line block)
+    int nitems;
+    double *buf0, *buf1, *buf2; // packed u buffers; index 0 is the caller's state
+    double *w, *rel, *ext, *chain;
+    double theta;
+};
 enum ResultFlag { FLAG_NONPOS = 1, FLAG_NAN = 2 };
 
 // Launchers (tf_kernels.hip). Each returns the launch status.
@@ -83,6 +114,13 @@ hipError_t launch_flux_divergence(int nx, int ny, double ids, double ids2, const
                                   const double *u, double alpha, double beta, const double *add,
                                   double *out, hipStream_t s);
 hipError_t launch_mass(const double *u, size_t n, double *partials, int nblocks, hipStream_t s);
+hipError_t launch_pass_ens(int dir, bool solve, bool p32, const EnsParams &e, hipStream_t s);
+hipError_t launch_chain_ens(const EnsParams &e, int dir, hipStream_t s);
+hipError_t launch_ens_control(FilmState *st, int nfilms, const EnsScheme &S, int *active_count, hipStream_t s);
+hipError_t launch_ens_begin(FilmState *st, int nfilms, hipStream_t s);
+hipError_t launch_ens_commit(const FilmDesc *desc, FilmState *st, int nfilms, double *buf0, double *buf1,
+                             double *buf2, hipStream_t s);
+hipError_t launch_ens_validate(const FilmDesc *desc, FilmState *st, int nfilms, const double *buf0, hipStream_t s);
 int mass_blocks(size_t n);
 
 } // namespace tf

@@ -438,7 +438,7 @@ __device__ __forceinline__ void sweep(const double *sU, const double *sB, const 
 }
 
 template <int DIR, bool SOLVE, bool P32>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SOLVE ? K3_WAVES_PER_EU : 2, SOLVE ? K3_WAVES_PER_EU : 2))) k_pass(PassParams p)
+__device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
 {
     __shared__ double sU[TW * UPITCH];
     __shared__ double sB[NSUB * NREL * 64];
@@ -447,9 +447,6 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SOLV
     static_assert(NSUB * NREL * 64 >= TILE * WPITCH, "second LDS region too small");
 
     const int nx = p.nx, ny = p.ny;
-    const int ntiles = p.tiles_x * p.tiles_y;
-    const int t = xcd_tile(blockIdx.x, ntiles);
-    const int tx = t % p.tiles_x, ty = t / p.tiles_x;
     int x0, x1, y0, y1;
     if (DIR == 0) {
         x0 = tx * LT0; x1 = min(x0 + LT0, nx);
@@ -461,7 +458,6 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SOLV
     const int bxo = DIR == 0 ? x0 - 1 : x0;  // grid x of lane/position 0 of the tile
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    if (p.res_clear != nullptr && blockIdx.x == 0 && tid < RES_WORDS) p.res_clear[tid] = 0ull;
 
     {
         // issue every global load of the tile before the first LDS store
@@ -625,6 +621,49 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SOLV
     }
 }
 
+#define TF_PASS_ATTR                                                                         \
+    __launch_bounds__(BLOCK)                                                                 \
+    __attribute__((amdgpu_waves_per_eu(SOLVE ? K3_WAVES_PER_EU : 2, SOLVE ? K3_WAVES_PER_EU : 2)))
+
+template <int DIR, bool SOLVE, bool P32>
+__global__ void TF_PASS_ATTR k_pass(PassParams p)
+{
+    if (p.res_clear != nullptr && blockIdx.x == 0 && threadIdx.x < RES_WORDS) p.res_clear[threadIdx.x] = 0ull;
+    const int t = xcd_tile(blockIdx.x, p.tiles_x * p.tiles_y);
+    tile_body<DIR, SOLVE, P32>(p, t % p.tiles_x, t / p.tiles_x);
+}
+
+// Ensemble version: block -> (film, tile) from the work list; the film's geometry,
+// model, dt and buffer rotation come from the device tables, so one launch (and one
+// captured graph) serves every film. Films that are not iterating exit at once.
+template <int DIR, bool SOLVE, bool P32>
+__global__ void TF_PASS_ATTR k_pass_ens(EnsParams e)
+{
+    const int t = xcd_tile(blockIdx.x, e.nitems);
+    const int f = e.items[3 * t], tx = e.items[3 * t + 1], ty = e.items[3 * t + 2];
+    FilmState *s = e.state + f;
+    if (!s->active) return;
+    const FilmDesc d = e.desc[f];
+    double *B[3] = {e.buf0, e.buf1, e.buf2};
+    PassParams p{};
+    p.nx = d.nx;
+    p.ny = d.ny;
+    p.ids = 1.0 / d.ds;
+    p.ids2 = 1.0 / (d.ds * d.ds);
+    const double c = e.theta * s->dt;
+    p.k1 = c / d.ds;
+    p.k3 = c / (d.ds * d.ds * d.ds * d.ds);
+    p.cD = c;
+    p.M = d.M;
+    p.u = B[s->it] + d.off;
+    p.in2 = DIR == 0 ? B[s->cur] + d.off : e.w + d.off;
+    p.out = DIR == 0 ? e.w + d.off : B[s->nxt] + d.off;
+    p.rel = e.rel + d.roff * NREL;
+    p.ext = e.ext + d.roff * NEXT;
+    p.res = s->red;
+    tile_body<DIR, SOLVE, P32>(p, tx, ty);
+}
+
 // ------------------------------------------------------------------------------------
 // Interface chain: per line, block elimination over the P segments (outer boundary
 // values are zero at the two ends of the line), then back-substitution giving every
@@ -641,10 +680,8 @@ __device__ __forceinline__ void load_rec(const double *r, size_t NL, double (&T)
         }
 }
 
-__global__ void __launch_bounds__(64) k_chain(ChainParams c)
+__device__ __forceinline__ void chain_body(const ChainParams &c, int line)
 {
-    const int line = blockIdx.x * 64 + threadIdx.x;
-    if (line >= c.nlines) return;
     const size_t NL = (size_t)c.nlines;
     const size_t RS = (size_t)NREL * NL; // stride between segment records
     double tau0 = 0.0, tau1 = 0.0, bt0 = 0.0, bt1 = 0.0;
@@ -724,6 +761,25 @@ __global__ void __launch_bounds__(64) k_chain(ChainParams c)
         tn1 = t1;
         for (int k = 0; k < 6; ++k) { cq[k] = nq[k]; cp[k] = cpp[k]; }
     }
+}
+
+__global__ void __launch_bounds__(64) k_chain(ChainParams c)
+{
+    const int line = blockIdx.x * 64 + threadIdx.x;
+    if (line < c.nlines) chain_body(c, line);
+}
+
+// Ensemble version: block -> (film, block of 64 lines); dir 0 chains the y sweep.
+__global__ void __launch_bounds__(64) k_chain_ens(EnsParams e, int dir)
+{
+    const int f = e.items[2 * blockIdx.x], lb = e.items[2 * blockIdx.x + 1];
+    const FilmState *s = e.state + f;
+    if (!s->active) return;
+    const FilmDesc d = e.desc[f];
+    ChainParams c{dir == 0 ? d.nx : d.ny, dir == 0 ? d.Py : d.Px, e.rel + d.roff * NREL, e.chain + d.roff * NCHAIN,
+                  e.ext + d.roff * NEXT};
+    const int line = lb * 64 + threadIdx.x;
+    if (line < c.nlines) chain_body(c, line);
 }
 
 // ------------------------------------------------------------------------------------
@@ -815,6 +871,137 @@ __global__ void __launch_bounds__(256) k_mass(const double *u, size_t n, double 
     }
 }
 
+
+// ------------------------------------------------------------------------------------
+// Ensemble control (Fig. FlowChartTime per film, on the device). One block; after
+// every iteration each iterating film reads its reduction record and either accepts,
+// continues, or rejects the attempt (shrinking dt when adaptive). The number of films
+// still iterating is left in active_count for the host.
+// ------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_ens_control(FilmState *st, int nfilms, EnsScheme S, int *active_count)
+{
+    __shared__ int cnt[256];
+    int mine = 0;
+    for (int f = threadIdx.x; f < nfilms; f += 256) {
+        FilmState &s = st[f];
+        if (!s.active) continue;
+        const double e = __longlong_as_double((long long)s.red[RES_EMAX]);
+        const double r = __longlong_as_double((long long)s.red[RES_RMAX]);
+        const unsigned long long flags = s.red[RES_FLAGS];
+        s.red[RES_EMAX] = 0ull;
+        s.red[RES_RMAX] = 0ull;
+        s.red[RES_FLAGS] = 0ull;
+        s.k += 1;
+        s.total += 1;
+        s.e_last = e;
+        s.r_last = r;
+        bool fail = false;
+        if (flags != 0ull) {
+            fail = true;                       // an iterate left the admissible set
+        } else if (e < S.tol) {                // accept u^{n+1} = u_{k+1}
+            s.cur = s.nxt;
+            s.newton = s.k;
+            s.dt_used = s.dt;
+            s.t += s.dt;
+            s.successes += 1;
+            if (S.adaptive && s.successes >= S.grow_after) {
+                s.dt = fmin(s.dt * S.dt_grow, S.dt_max);
+                s.successes = 0;
+            }
+            s.active = 0;
+            s.status = 0;
+        } else if (s.k >= S.max_newton) {
+            fail = true;
+        } else {                               // continue from u_{k+1}
+            s.it = s.nxt;
+            s.nxt = 3 - s.cur - s.it;
+        }
+        if (fail) {
+            s.rejections += 1;
+            s.successes = 0;
+            s.dt_used = s.dt;
+            if (!S.adaptive) {
+                s.active = 0;
+                s.status = 4; // TF_ENOCONV
+            } else {
+                s.dt *= S.dt_shrink;
+                if (s.dt < S.dt_min) {
+                    s.active = 0;
+                    s.status = 4;
+                } else {                       // retry from u^n
+                    s.k = 0;
+                    s.it = s.cur;
+                    s.nxt = s.cur == 0 ? 1 : 0;
+                }
+            }
+        }
+        if (s.active) ++mine;
+    }
+    cnt[threadIdx.x] = mine;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) active_count[0] = cnt[0];
+}
+
+__global__ void __launch_bounds__(256) k_ens_begin(FilmState *st, int nfilms)
+{
+    const int f = blockIdx.x * 256 + threadIdx.x;
+    if (f >= nfilms) return;
+    FilmState &s = st[f];
+    if (s.status != 0) return;
+    s.active = 1;
+    s.k = 0;
+    s.it = s.cur;
+    s.nxt = s.cur == 0 ? 1 : 0;
+    s.rejections = 0;
+    s.red[RES_EMAX] = 0ull;
+    s.red[RES_RMAX] = 0ull;
+    s.red[RES_FLAGS] = 0ull;
+}
+
+// Copy every film's accepted state back into buffer 0 (the caller's).
+__global__ void __launch_bounds__(256) k_ens_commit(const FilmDesc *desc, FilmState *st, double *buf0, double *buf1,
+                                                    double *buf2)
+{
+    const int f = blockIdx.x;
+    const int cur = st[f].cur;
+    if (cur != 0) {
+        const FilmDesc d = desc[f];
+        const double *src = (cur == 1 ? buf1 : buf2) + d.off;
+        double *dst = buf0 + d.off;
+        const size_t n = (size_t)d.nx * d.ny;
+        for (size_t i = threadIdx.x; i < n; i += 256) dst[i] = src[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) st[f].cur = 0;
+}
+
+// Mark films whose state holds h <= 0 or NaN (TF_ENONPOS).
+__global__ void __launch_bounds__(256) k_ens_validate(const FilmDesc *desc, FilmState *st, const double *buf0)
+{
+    __shared__ int bad[256];
+    const int f = blockIdx.x;
+    const FilmDesc d = desc[f];
+    const double *u = buf0 + d.off;
+    const size_t n = (size_t)d.nx * d.ny;
+    int b = 0;
+    for (size_t i = threadIdx.x; i < n; i += 256)
+        if (!(u[i] > 0.0)) b = 1;
+    bad[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) bad[threadIdx.x] |= bad[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && bad[0]) {
+        st[f].status = 5; // TF_ENONPOS
+        st[f].active = 0;
+    }
+}
+
 // ---- launchers -----------------------------------------------------------------------
 hipError_t launch_pass(int dir, bool solve, const PassParams &p, hipStream_t s)
 {
@@ -859,6 +1046,58 @@ int mass_blocks(size_t n)
 hipError_t launch_mass(const double *u, size_t n, double *partials, int nblocks, hipStream_t s)
 {
     k_mass<<<dim3(nblocks), dim3(256), 0, s>>>(u, n, partials);
+    return hipGetLastError();
+}
+
+} // namespace tf
+
+namespace tf {
+
+hipError_t launch_pass_ens(int dir, bool solve, bool p32, const EnsParams &e, hipStream_t s)
+{
+    const dim3 grid(e.nitems), block(BLOCK);
+    if (p32) {
+        if (dir == 0 && !solve) k_pass_ens<0, false, true><<<grid, block, 0, s>>>(e);
+        else if (dir == 0) k_pass_ens<0, true, true><<<grid, block, 0, s>>>(e);
+        else if (!solve) k_pass_ens<1, false, true><<<grid, block, 0, s>>>(e);
+        else k_pass_ens<1, true, true><<<grid, block, 0, s>>>(e);
+    } else {
+        if (dir == 0 && !solve) k_pass_ens<0, false, false><<<grid, block, 0, s>>>(e);
+        else if (dir == 0) k_pass_ens<0, true, false><<<grid, block, 0, s>>>(e);
+        else if (!solve) k_pass_ens<1, false, false><<<grid, block, 0, s>>>(e);
+        else k_pass_ens<1, true, false><<<grid, block, 0, s>>>(e);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_ens(const EnsParams &e, int dir, hipStream_t s)
+{
+    k_chain_ens<<<dim3(e.nitems), dim3(64), 0, s>>>(e, dir);
+    return hipGetLastError();
+}
+
+hipError_t launch_ens_control(FilmState *st, int nfilms, const EnsScheme &S, int *active_count, hipStream_t s)
+{
+    k_ens_control<<<dim3(1), dim3(256), 0, s>>>(st, nfilms, S, active_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_ens_begin(FilmState *st, int nfilms, hipStream_t s)
+{
+    k_ens_begin<<<dim3((nfilms + 255) / 256), dim3(256), 0, s>>>(st, nfilms);
+    return hipGetLastError();
+}
+
+hipError_t launch_ens_commit(const FilmDesc *desc, FilmState *st, int nfilms, double *buf0, double *buf1,
+                             double *buf2, hipStream_t s)
+{
+    k_ens_commit<<<dim3(nfilms), dim3(256), 0, s>>>(desc, st, buf0, buf1, buf2);
+    return hipGetLastError();
+}
+
+hipError_t launch_ens_validate(const FilmDesc *desc, FilmState *st, int nfilms, const double *buf0, hipStream_t s)
+{
+    k_ens_validate<<<dim3(nfilms), dim3(256), 0, s>>>(desc, st, buf0);
     return hipGetLastError();
 }
 

@@ -70,6 +70,17 @@ def lib():
         L.tf_profile.argtypes = [P, C.c_int]
         L.tf_profile_read.argtypes = [P, C.POINTER(D), C.POINTER(C.c_long), C.c_int]
         L.tf_profile_read.restype = C.c_int
+        IP = C.POINTER(C.c_int)
+        DP = C.POINTER(D)
+        L.tf_ensemble_create.argtypes = [C.c_int, IP, IP, DP, DP, D, D, D, P, C.POINTER(P)]
+        L.tf_ensemble_destroy.argtypes = [P]
+        L.tf_ensemble_set_scheme.argtypes = [P, C.POINTER(Scheme)]
+        L.tf_ensemble_size.argtypes = [P]
+        L.tf_ensemble_size.restype = C.c_longlong
+        L.tf_ensemble_offsets.argtypes = [P, C.POINTER(C.c_longlong)]
+        L.tf_ensemble_bind.argtypes = [P, P]
+        L.tf_ensemble_step.argtypes = [P, C.c_int, DP, IP, IP]
+        L.tf_ensemble_film_info.argtypes = [P, C.c_int, C.POINTER(StepInfo)]
         _lib = L
     return _lib
 
@@ -205,3 +216,68 @@ class Grid:
         cnt = (C.c_long * n)()
         lib().tf_profile_read(self._h, ms, cnt, n)
         return {names[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
+class Ensemble:
+    """Films of different sizes / kappa / ds packed in one buffer and stepped in lockstep
+    (include/thinfilm.h, tf_ensemble_*). Backward Euler only."""
+
+    def __init__(self, nx, ny, ds, kappa, b=0.1, n=3, m=2, stream=None):
+        k = len(nx)
+        self.nfilms = k
+        self._h = C.c_void_p()
+        ia = (C.c_int * k)(*[int(v) for v in nx])
+        ja = (C.c_int * k)(*[int(v) for v in ny])
+        da = (C.c_double * k)(*[float(v) for v in ds])
+        ka = (C.c_double * k)(*[float(v) for v in kappa])
+        _check(lib().tf_ensemble_create(k, ia, ja, da, ka, float(b), float(n), float(m), _stream_ptr(stream),
+                                        C.byref(self._h)))
+        self.nx, self.ny = list(nx), list(ny)
+        offs = (C.c_longlong * k)()
+        _check(lib().tf_ensemble_offsets(self._h, offs))
+        self.offsets = [int(v) for v in offs]
+        self.size = int(lib().tf_ensemble_size(self._h))
+        self._state = None
+
+    def close(self):
+        if self._h:
+            lib().tf_ensemble_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_scheme(self, **kw):
+        s = default_scheme(**kw)
+        _check(lib().tf_ensemble_set_scheme(self._h, C.byref(s)))
+        return self
+
+    def view(self, packed, f):
+        """(ny, nx) view of film f inside the packed tensor."""
+        o = self.offsets[f]
+        return packed[o:o + self.nx[f] * self.ny[f]].view(self.ny[f], self.nx[f])
+
+    def bind(self, packed):
+        if packed.numel() != self.size:
+            raise ValueError(f"packed buffer must hold {self.size} doubles")
+        _check(lib().tf_ensemble_bind(self._h, _ptr(packed)))
+        self._state = packed
+        return self
+
+    def step(self, nsteps, dt):
+        """Advance every film nsteps; dt: float or per-film list. Returns (status, dts,
+        statuses, iterations)."""
+        k = self.nfilms
+        dts = (C.c_double * k)(*([float(dt)] * k if isinstance(dt, (int, float)) else [float(v) for v in dt]))
+        sts = (C.c_int * k)()
+        its = (C.c_int * k)()
+        st = lib().tf_ensemble_step(self._h, int(nsteps), dts, sts, its)
+        return st, list(dts), list(sts), list(its)
+
+    def film_info(self, f):
+        info = StepInfo()
+        _check(lib().tf_ensemble_film_info(self._h, int(f), C.byref(info)))
+        return info.as_dict()

@@ -1,0 +1,113 @@
+"""Ensemble path (packed ragged films, device-side control, captured graph) against the
+single-film GPU path (bit for bit: same kernels, same arithmetic) and the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1806_10550_amd import synth
+from paper_1806_10550_amd.lib import Ensemble, Grid, TF_ENONPOS, TF_ENOCONV, TF_OK
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+FILMS = [(70, 66, 5.0), (64, 64, 10.0), (130, 40, 20.0), (200, 129, 8.0), (96, 96, 15.0), (4, 9, 12.0)]
+
+
+def films_setup(films, amp=0.01):
+    nx = [f[0] for f in films]
+    ny = [f[1] for f in films]
+    kap = [f[2] for f in films]
+    ds = [8 * synth.lambda_m(k) / n for n, _, k in films]
+    h0 = [synth.noise_film(a, b, seed=100 + i, amp=amp) for i, (a, b, _) in enumerate(films)]
+    return nx, ny, kap, ds, h0
+
+
+def pack(ens, h0):
+    packed = torch.empty(ens.size, dtype=torch.float64, device=DEV)
+    for f, h in enumerate(h0):
+        ens.view(packed, f).copy_(torch.from_numpy(h))
+    return packed
+
+
+def single(nx, ny, ds, kappa, h0, steps, dt, **scheme):
+    g = Grid(nx, ny, ds)
+    g.set_model(kappa, 0.1, 3, 2)
+    g.set_scheme(**scheme)
+    h = torch.from_numpy(h0).to(DEV)
+    g.bind(h)
+    st, dtn, log = g.try_advance(steps, dt)
+    return st, dtn, log, h
+
+
+def test_ensemble_equals_single_film_path_bitwise():
+    nx, ny, kap, ds, h0 = films_setup(FILMS)
+    ens = Ensemble(nx, ny, ds, kap)
+    ens.set_scheme(tol=1e-10)
+    packed = pack(ens, h0)
+    ens.bind(packed)
+    st, dts, sts, its = ens.step(4, 0.1)
+    assert st == TF_OK and all(s == TF_OK for s in sts)
+    for f in range(len(FILMS)):
+        s1, _, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 4, 0.1, tol=1e-10)
+        assert s1 == TF_OK
+        assert torch.equal(ens.view(packed, f), h), f
+        assert its[f] == sum(x["total_iters"] for x in log)
+
+
+def test_ensemble_matches_oracle(orc):
+    nx, ny, kap, ds, h0 = films_setup(FILMS[:4])
+    ens = Ensemble(nx, ny, ds, kap)
+    packed = pack(ens, h0)
+    ens.bind(packed)
+    st, _, sts, _ = ens.step(3, 0.1)
+    assert st == TF_OK
+    for f in range(4):
+        M = orc.Model(kappa=kap[f], b=0.1, n=3.0, m=2.0)
+        u = h0[f]
+        for _ in range(3):
+            u, res = orc.step(M, orc.Scheme(tol=1e-10), u, ds[f], 0.1)
+            assert res.status == orc.OK
+        got = ens.view(packed, f).cpu().numpy()
+        assert np.max(np.abs(got - u) / u) <= 1e-10
+
+
+def test_ensemble_failure_is_isolated():
+    nx, ny, kap, ds, h0 = films_setup(FILMS[:3])
+    h0[1] = h0[1].copy()
+    h0[1][3, 3] = -0.2
+    ens = Ensemble(nx, ny, ds, kap)
+    packed = pack(ens, h0)
+    ens.bind(packed)
+    st, _, sts, _ = ens.step(2, 0.1)
+    assert st == TF_ENONPOS
+    assert sts == [TF_OK, TF_ENONPOS, TF_OK]
+    assert torch.equal(ens.view(packed, 1).cpu(), torch.from_numpy(h0[1]))
+    # a fixed-dt film that cannot converge within max_newton fails alone
+    ens2 = Ensemble(nx, ny, ds, kap)
+    ens2.set_scheme(max_newton=1, tol=1e-14)
+    h1 = films_setup(FILMS[:3])[4]
+    p2 = pack(ens2, h1)
+    ens2.bind(p2)
+    st, _, sts, _ = ens2.step(1, 0.1)
+    assert st == TF_ENOCONV and all(s == TF_ENOCONV for s in sts)
+    for f in range(3):
+        assert torch.equal(ens2.view(p2, f).cpu(), torch.from_numpy(h1[f]))
+
+
+def test_ensemble_adaptive_schedules_match_single_films():
+    nx, ny, kap, ds, h0 = films_setup(FILMS[:5])
+    kw = dict(tol=1e-10, max_newton=10, adaptive=1, dt_min=1e-6, dt_max=1.0, dt_shrink=0.5, dt_grow=1.1,
+              grow_after=5)
+    ens = Ensemble(nx, ny, ds, kap)
+    ens.set_scheme(**kw)
+    packed = pack(ens, h0)
+    ens.bind(packed)
+    dts = [0.1] * 5
+    for _ in range(3):
+        st, dts, sts, its = ens.step(4, dts)
+        assert st == TF_OK
+    for f in range(5):
+        s1, dtn, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 12, 0.1, **kw)
+        assert s1 == TF_OK
+        assert dts[f] == dtn
+        assert torch.equal(ens.view(packed, f), h), f
