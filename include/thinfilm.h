@@ -154,6 +154,46 @@ tf_status tf_ensemble_step(tf_ensemble *e, int nsteps, double *dt_per_film, int 
 /* Record of film `film` after the last tf_ensemble_step (time, last dt, iterations). */
 tf_status tf_ensemble_film_info(const tf_ensemble *e, int film, tf_step_info *info);
 
+/* ---- Discrete adjoint ----------------------------------------------------------------
+ * Adjoint of one converged step u^{n+1} = S(u^n, kappa), S defined implicitly by
+ * G(u^{n+1}; u^n, kappa) = u^{n+1} - u^n + dt[theta D(u^{n+1}) + (1-theta) D(u^n)] = 0
+ * (eq. TrapRule in theta form; the grid's model and theta are used). Given
+ * lambda^{n+1} = dL/du^{n+1} (device, in lambda_inout) it solves
+ *     (I + theta dt J_D(u^{n+1}))^T mu = lambda^{n+1}
+ * by Richardson iteration preconditioned with the transposed ADI factors
+ * (I + c J_y)^-T (I + c J_x)^-T (eqs. DirectionSplit, JacobianSystem1-2) until
+ * max|dmu| <= tol max|mu| (at most max_iter iterations; TF_ENOCONV otherwise), then
+ * writes lambda^n = mu - (1-theta) dt J_D(u^n)^T mu into lambda_inout and adds
+ * -dt mu . [theta dD/dkappa(u^{n+1}) + (1-theta) dD/dkappa(u^n)] to *dL_dkappa_accum
+ * (host, nullable). h_n, h_np1: the two time levels (device, nx*ny each, unchanged).
+ * iters_out (host, nullable): Richardson iterations used. */
+tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, double dt, double *lambda_inout,
+                          double *dL_dkappa_accum, double tol, int max_iter, int *iters_out);
+/* out = J_D(u)^T mu with the full analytic Jacobian of the flux-difference operator D
+ * (device arrays, nx*ny each). */
+tf_status tf_jacobian_apply_t(tf_grid *g, const double *u, const double *mu, double *out);
+
+/* ---- Batched pentadiagonal solves on stored bands -----------------------------------
+ * nlines independent systems of n unknowns (n >= 2). Layout position-major: element
+ * (position p, line l) at p*nlines + l. bands: 5 device arrays of n*nlines doubles back
+ * to back (a, b, c, d, e = offsets -2..+2: row p of line l reads x at p-2..p+2 with
+ * coefficients a..e at (p, l); entries reaching outside the line must be zero).
+ * transposed != 0 solves with the transposed matrices. variant: 0 = partitioned
+ * (64-cell segments, interface chain), 1 = one lane per line (Thomas), -1 = the
+ * autotuned choice. No pivoting: the matrices must be LU-factorable without it.
+ * Allocates and frees its own scratch; synchronises `stream`. */
+tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *rhs, double *x, int transposed,
+                         int variant, void *stream);
+/* Time both variants on random diagonally dominant systems of the given length and
+ * batch, remember the faster one for solves of similar shape (used by tf_adjoint_step
+ * and tf_penta_solve with variant -1), and append a JSON line {arch, length, batch,
+ * variant, ms} to cache_path (nullable). tf_autotune_load reads such a file (entries
+ * of the current GPU architecture only). tf_autotune_choice returns the variant that
+ * would be used (0 or 1). */
+tf_status tf_autotune(int length, int batch, const char *cache_path);
+tf_status tf_autotune_load(const char *cache_path);
+int tf_autotune_choice(int length, int batch);
+
 /* Description of the calling thread's most recent error (never NULL). */
 const char *tf_last_error(void);
 

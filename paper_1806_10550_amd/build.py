@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libthinfilm.so")
-SOURCES = ["tf_kernels.hip", "tf_api.hip", "tf_ensemble.hip"]
+SOURCES = ["tf_kernels.hip", "tf_api.hip", "tf_ensemble.hip", "tf_adjoint.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,853 @@
+// Discrete adjoint of the converged ADI-Newton step and the stored-band batched
+// pentadiagonal solvers it uses (see include/thinfilm.h: tf_adjoint_step,
+// tf_penta_solve, tf_autotune).
+//
+// The adjoint differentiates the implicit step map G(u^{n+1}; u^n, kappa) = 0 with
+// G = u - u^n + dt[theta D(u) + (1 - theta) D(u^n)] (eq. TrapRule in theta form):
+//   (I + theta dt J_D(u^{n+1}))^T mu = lambda^{n+1},
+//   lambda^n = mu - (1 - theta) dt J_D(u^n)^T mu,
+//   dL/dkappa -= dt mu . [theta dD/dkappa(u^{n+1}) + (1 - theta) dD/dkappa(u^n)].
+// The transposed system is solved by Richardson iteration preconditioned with the
+// transposed ADI factors P^-T = (I + c J_y)^-T (I + c J_x)^-T (a transposed row solve,
+// then a transposed column solve), the same split as the forward Newton iteration
+// (eqs. DirectionSplit, JacobianSystem1-2).
+#include "tf_device.h"
+#include "../../include/thinfilm.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+namespace tf {
+
+// ---- cell quantities straight from global memory (reflected ghosts) -------------------
+template <bool P32>
+__device__ __forceinline__ Cell cell_glob(const double *u, int nx, int ny, int i, int j, const Model &M, double ids2)
+{
+    const int ic = crefl(i, nx), jc = crefl(j, ny);
+    const int im = crefl(ic - 1, nx), ip = crefl(ic + 1, nx), jm = crefl(jc - 1, ny), jp = crefl(jc + 1, ny);
+    Cell c;
+    c.u = u[(size_t)jc * nx + ic];
+    c.lap = (u[(size_t)jc * nx + ip] + u[(size_t)jc * nx + im] + u[(size_t)jp * nx + ic] + u[(size_t)jm * nx + ic]
+             - 4.0 * c.u) * ids2;
+    model_coefs<P32>(M, c.u, c.f0, c.f1, c.f0p, c.f1p);
+    c.f0p *= 0.5;
+    c.f1p *= 0.5;
+    return c;
+}
+
+// Bands (a, b, c, d, e) of I + c J along direction DIR at every cell, stored
+// position-major for the stored-band solver: DIR 0 (y) as [j][i], DIR 1 (x) as [i][j].
+template <int DIR, bool P32>
+__global__ void __launch_bounds__(256) k_bands_store(int nx, int ny, double ids, double ids2, double k1, double k3,
+                                                     Model M, const double *u, double *bands)
+{
+    // DIR 0: lanes along i; DIR 1: lanes along j (coalesced stores of the [i][j] layout)
+    const int a0 = blockIdx.x * 64 + (threadIdx.x & 63), b0 = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int i = DIR == 0 ? a0 : b0, j = DIR == 0 ? b0 : a0;
+    if (i >= nx || j >= ny) return;
+    const int Np = DIR == 0 ? ny : nx;
+    const int gp = DIR == 0 ? j : i;
+    const int di = DIR == 0 ? 0 : 1, dj = DIR == 0 ? 1 : 0;
+    const Cell cm = cell_glob<P32>(u, nx, ny, i - di, j - dj, M, ids2);
+    const Cell c0 = cell_glob<P32>(u, nx, ny, i, j, M, ids2);
+    const Cell cp = cell_glob<P32>(u, nx, ny, i + di, j + dj, M, ids2);
+    const FaceQ fm = face_q<false>(cm, c0, gp > 0, ids, k1, k3);
+    const FaceQ fp = face_q<false>(c0, cp, gp < Np - 1, ids, k1, k3);
+    double a = fm.kA;
+    double b = -fp.kA - 3.0 * fm.kA - fm.P;
+    double c = 1.0 + 3.0 * fp.kA + fp.P + 3.0 * fm.kA - fm.Q;
+    double d = -3.0 * fp.kA + fp.Q - fm.kA;
+    double e = fp.kA;
+    if (gp == 0) { c += b; d += a; b = 0.0; a = 0.0; }
+    else if (gp == 1) { b += a; a = 0.0; }
+    if (gp == Np - 1) { c += d; b += e; d = 0.0; e = 0.0; }
+    else if (gp == Np - 2) { d += e; e = 0.0; }
+    const size_t N = (size_t)nx * ny;
+    const size_t o = DIR == 0 ? (size_t)j * nx + i : (size_t)i * ny + j;
+    bands[o] = a;
+    bands[N + o] = b;
+    bands[2 * N + o] = c;
+    bands[3 * N + o] = d;
+    bands[4 * N + o] = e;
+}
+
+// ---- stored-band batched pentadiagonal solves ------------------------------------------
+// Data layout [position][line] (lanes = consecutive lines); bands as 5 arrays a..e.
+// TRANS: solve with the transposed matrix, whose row p is
+//   (e_{p-2}, d_{p-1}, c_p, b_{p+1}, a_{p+2}).
+template <bool TRANS>
+__device__ __forceinline__ void load_band_row(const double *bands, size_t N, int nl, int np, int p, int line,
+                                              double &a, double &b, double &c, double &d, double &e)
+{
+    const size_t o = (size_t)p * nl + line;
+    if (!TRANS) {
+        a = bands[o]; b = bands[N + o]; c = bands[2 * N + o]; d = bands[3 * N + o]; e = bands[4 * N + o];
+    } else {
+        a = p >= 2 ? bands[4 * N + o - 2 * (size_t)nl] : 0.0;
+        b = p >= 1 ? bands[3 * N + o - (size_t)nl] : 0.0;
+        c = bands[2 * N + o];
+        d = p + 1 < np ? bands[N + o + (size_t)nl] : 0.0;
+        e = p + 2 < np ? bands[o + 2 * (size_t)nl] : 0.0;
+    }
+}
+
+// LU elimination over a (sub-)segment with its two left outer unknowns kept symbolic
+// and two rows of the inverse upper factor accumulated on the fly (same algebra as the
+// forward sweep): yields the segment's top/bottom relation record.
+struct Elim {
+    double al1 = 0.0, be1 = 0.0, al2 = 0.0, be2 = 0.0;
+    double z1 = 0.0, ph1 = 0.0, ps1 = 1.0, z2 = 0.0, ph2 = 1.0, ps2 = 0.0;
+    double g1 = 0.0, g2 = 0.0, h1 = 0.0, h2 = 0.0;
+    double sgz = 0.0, sgph = 0.0, sgps = 0.0, shz = 0.0, shph = 0.0, shps = 0.0;
+    __device__ __forceinline__ void step(int k, double a, double b, double c, double d, double e, double rhs,
+                                         double &al, double &be, double &z, double &ph, double &pss)
+    {
+        const double gam = b - a * al2;
+        const double mu = c - a * be2 - gam * al1;
+        const double rm = rcp(mu);
+        al = (d - gam * be1) * rm;
+        be = e * rm;
+        z = (rhs - a * z2 - gam * z1) * rm;
+        ph = (-a * ph2 - gam * ph1) * rm;
+        pss = (-a * ps2 - gam * ps1) * rm;
+        const double g = k == 0 ? 1.0 : -al1 * g1 - be2 * g2;
+        const double h = k == 1 ? 1.0 : (k == 0 ? 0.0 : -al1 * h1 - be2 * h2);
+        sgz += g * z; sgph += g * ph; sgps += g * pss;
+        shz += h * z; shph += h * ph; shps += h * pss;
+        g2 = g1; g1 = g; h2 = h1; h1 = h;
+        al2 = al1; be2 = be1; al1 = al; be1 = be;
+        z2 = z1; ph2 = ph1; ps2 = ps1; z1 = z; ph1 = ph; ps1 = pss;
+    }
+    __device__ __forceinline__ void finish(Rel &r) const
+    {
+        r.B[1][0] = z1; r.B[1][1] = ph1; r.B[1][2] = ps1; r.B[1][3] = -al1; r.B[1][4] = -be1;
+        r.B[0][0] = z2 - al2 * z1; r.B[0][1] = ph2 - al2 * ph1; r.B[0][2] = ps2 - al2 * ps1;
+        r.B[0][3] = -be2 + al2 * al1; r.B[0][4] = al2 * be1;
+        r.T[0][0] = sgz; r.T[0][1] = sgph; r.T[0][2] = sgps;
+        r.T[0][3] = -g2 * be2 - g1 * al1; r.T[0][4] = -g1 * be1;
+        r.T[1][0] = shz; r.T[1][1] = shph; r.T[1][2] = shps;
+        r.T[1][3] = -h2 * be2 - h1 * al1; r.T[1][4] = -h1 * be1;
+    }
+};
+
+struct SBParams {
+    int nl, np;               // lines, cells per line
+    const double *bands;      // 5 arrays of nl*np
+    const double *rhs;
+    double *out;              // MODE 0: x; MODE 1: out += x
+    double *rel;
+    const double *ext;
+    unsigned long long *red;  // MODE 1: {max|x|, max|out|}
+};
+
+// Partitioned solve over tiles of 64 lines x 64 cells (4 waves x 16-cell sub-segments):
+// SOLVE false emits the tile's relation record per line, SOLVE true back-substitutes.
+template <bool SOLVE, bool TRANS, int MODE>
+__global__ void __launch_bounds__(BLOCK) k_sb_pass(SBParams P)
+{
+    __shared__ double sB[NSUB * NREL * 64];
+    __shared__ double sRed[NSUB][2];
+    const int nlg = (P.nl + 63) / 64;
+    const int t = xcd_tile(blockIdx.x, nlg * seg_count(P.np));
+    const int lg = t % nlg, q = t / nlg;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int line = lg * 64 + lane;
+    const bool owned = line < P.nl;
+    const int lc = owned ? line : P.nl - 1;
+    const int s0 = seg_start(q, P.np), s1 = seg_start(q + 1, P.np);
+    const int npos = s1 - s0;
+    const int nsub = min(NSUB, npos / 2);
+    const int ps = (wave * npos) / nsub;
+    const int len = wave < nsub ? ((wave + 1) * npos) / nsub - ps : 0;
+    const size_t N = (size_t)P.nl * P.np;
+    double fa[SUB], fb[SUB], fz[SUB], fph[SUB], fps[SUB];
+    Rel mine;
+    if (len > 0) {
+        Elim E;
+#pragma unroll
+        for (int k = 0; k < SUB; ++k) {
+            if (k < len) {
+                const int p = s0 + ps + k;
+                double a, b, c, d, e;
+                load_band_row<TRANS>(P.bands, N, P.nl, P.np, p, lc, a, b, c, d, e);
+                const double rhs = P.rhs[(size_t)p * P.nl + lc];
+                double al, be, z, ph, pss;
+                E.step(k, a, b, c, d, e, rhs, al, be, z, ph, pss);
+                if (SOLVE) { fa[k] = al; fb[k] = be; fz[k] = z; fph[k] = ph; fps[k] = pss; }
+            }
+        }
+        E.finish(mine);
+        double *dst = sB + (size_t)wave * NREL * 64 + lane;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                dst[(i * 5 + j) * 64] = mine.T[i][j];
+                dst[(10 + i * 5 + j) * 64] = mine.B[i][j];
+            }
+    }
+    __syncthreads();
+    if (!SOLVE) {
+        if (wave == 0 && owned) {
+            Rel seg;
+            chain_symbolic(sB, lane, nsub, seg);
+            double *o = P.rel + (size_t)q * NREL * P.nl + line;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 5; ++j) {
+                    o[(size_t)(i * 5 + j) * P.nl] = seg.T[i][j];
+                    o[(size_t)(10 + i * 5 + j) * P.nl] = seg.B[i][j];
+                }
+        }
+        return;
+    }
+    double xm = 0.0, om = 0.0;
+    if (len > 0) {
+        const double *ex = P.ext + (size_t)q * NEXT * P.nl + lc;
+        double wl1, wl2, xr1, xr2;
+        chain_numeric(sB, lane, nsub, wave, ex[0], ex[(size_t)P.nl], ex[(size_t)2 * P.nl], ex[(size_t)3 * P.nl],
+                      wl1, wl2, xr1, xr2);
+#pragma unroll
+        for (int k = SUB - 1; k >= 0; --k) {
+            if (k < len) {
+                const double x = fz[k] + fph[k] * wl1 + fps[k] * wl2 - fa[k] * xr1 - fb[k] * xr2;
+                xr2 = xr1;
+                xr1 = x;
+                if (owned) {
+                    const size_t o = (size_t)(s0 + ps + k) * P.nl + line;
+                    if (MODE == 0) {
+                        P.out[o] = x;
+                    } else {
+                        const double v = P.out[o] + x;
+                        P.out[o] = v;
+                        xm = fmax(xm, fabs(x));
+                        om = fmax(om, fabs(v));
+                        if (x != x) xm = __builtin_nan("");
+                    }
+                }
+            }
+        }
+    }
+    if (MODE == 1) {
+        const double wx = wave_max(xm), wo = wave_max(om);
+        if (lane == 0) { sRed[wave][0] = wx; sRed[wave][1] = wo; }
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0.0, b = 0.0;
+            for (int w = 0; w < NSUB; ++w) { a = fmax(a, sRed[w][0]); b = fmax(b, sRed[w][1]); }
+            atomicMax(&P.red[0], (unsigned long long)__double_as_longlong(a));
+            atomicMax(&P.red[1], (unsigned long long)__double_as_longlong(b));
+        }
+    }
+}
+
+// Interleaved Thomas: one lane per line over the whole line, factors kept in a
+// position-major workspace (3 doubles per cell), then back-substitution.
+template <bool TRANS, int MODE>
+__global__ void __launch_bounds__(64) k_sb_thomas(SBParams P, double *work)
+{
+    const int line = blockIdx.x * 64 + threadIdx.x;
+    double xm = 0.0, om = 0.0;
+    const size_t N = (size_t)P.nl * P.np;
+    if (line < P.nl) {
+        double al1 = 0.0, be1 = 0.0, al2 = 0.0, be2 = 0.0, z1 = 0.0, z2 = 0.0;
+        for (int p = 0; p < P.np; ++p) {
+            double a, b, c, d, e;
+            load_band_row<TRANS>(P.bands, N, P.nl, P.np, p, line, a, b, c, d, e);
+            const double rhs = P.rhs[(size_t)p * P.nl + line];
+            const double gam = b - a * al2;
+            const double mu = c - a * be2 - gam * al1;
+            const double rm = rcp(mu);
+            const double al = (d - gam * be1) * rm, be = e * rm, z = (rhs - a * z2 - gam * z1) * rm;
+            const size_t o = (size_t)p * P.nl + line;
+            work[o] = al;
+            work[N + o] = be;
+            work[2 * N + o] = z;
+            al2 = al1; be2 = be1; al1 = al; be1 = be; z2 = z1; z1 = z;
+        }
+        double x1 = 0.0, x2 = 0.0;
+        for (int p = P.np - 1; p >= 0; --p) {
+            const size_t o = (size_t)p * P.nl + line;
+            const double x = work[2 * N + o] - work[o] * x1 - work[N + o] * x2;
+            x2 = x1;
+            x1 = x;
+            if (MODE == 0) {
+                P.out[o] = x;
+            } else {
+                const double v = P.out[o] + x;
+                P.out[o] = v;
+                xm = fmax(xm, fabs(x));
+                om = fmax(om, fabs(v));
+                if (x != x) xm = __builtin_nan("");
+            }
+        }
+    }
+    if (MODE == 1) {
+        const double wx = wave_max(xm), wo = wave_max(om);
+        if (threadIdx.x == 0) {
+            atomicMax(&P.red[0], (unsigned long long)__double_as_longlong(wx));
+            atomicMax(&P.red[1], (unsigned long long)__double_as_longlong(wo));
+        }
+    }
+}
+
+// ---- transposed Jacobian apply ---------------------------------------------------------
+// J_D^T mu = local + L(xi) with, over the four faces f of a cell (omega_f = (mu_L - mu_R)/ds):
+//   local_c = sum_f omega_f [ f0'_c Lam_f / 2 + f1'_c Gam_f / 2 -+ B_f / ds ]  (- if c = L)
+//   xi_c    = sum_f omega_f A_f (+1 if c = R, -1 if c = L) / ds
+// and L the cell-centred Laplacian (symmetric under the even reflection).
+template <bool P32>
+__global__ void __launch_bounds__(256) k_jdt_xi(int nx, int ny, double ids, double ids2, Model M, const double *u,
+                                                const double *mu, double *xi, double *loc)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63), j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= nx || j >= ny) return;
+    const Cell c = cell_glob<P32>(u, nx, ny, i, j, M, ids2);
+    const double mc = mu[(size_t)j * nx + i];
+    double lo = 0.0, x = 0.0;
+    const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+    const bool inside[4] = {i > 0, i < nx - 1, j > 0, j < ny - 1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (!inside[k]) continue;
+        const int ni = i + di[k], nj = j + dj[k];
+        const Cell n = cell_glob<P32>(u, nx, ny, ni, nj, M, ids2);
+        const double mn = mu[(size_t)nj * nx + ni];
+        const bool cIsR = (k == 0 || k == 2); // neighbour is the lower-index cell L
+        const double A = 0.5 * (cIsR ? n.f0 + c.f0 : c.f0 + n.f0);
+        const double B = 0.5 * (cIsR ? n.f1 + c.f1 : c.f1 + n.f1);
+        const double Lam = (cIsR ? c.lap - n.lap : n.lap - c.lap) * ids;
+        const double Gam = (cIsR ? c.u - n.u : n.u - c.u) * ids;
+        const double om = (cIsR ? mn - mc : mc - mn) * ids;
+        lo += om * (c.f0p * Lam + c.f1p * Gam + (cIsR ? B * ids : -B * ids));
+        x += (cIsR ? om * A : -om * A) * ids;
+    }
+    xi[(size_t)j * nx + i] = x;
+    loc[(size_t)j * nx + i] = lo;
+}
+
+// out = a lam + b mu + g (local + L(xi))
+__global__ void __launch_bounds__(256) k_jdt_out(int nx, int ny, double ids2, const double *xi, const double *loc,
+                                                 const double *lam, const double *mu, double a, double b, double g,
+                                                 double *out)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63), j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= nx || j >= ny) return;
+    const size_t o = (size_t)j * nx + i;
+    const int im = crefl(i - 1, nx), ip = crefl(i + 1, nx), jm = crefl(j - 1, ny), jp = crefl(j + 1, ny);
+    const double lx = (xi[(size_t)j * nx + ip] + xi[(size_t)j * nx + im] + xi[(size_t)jp * nx + i]
+                       + xi[(size_t)jm * nx + i] - 4.0 * xi[o]) * ids2;
+    double v = g * (loc[o] + lx);
+    if (b != 0.0) v += b * mu[o];
+    if (a != 0.0) v += a * lam[o];
+    out[o] = v;
+}
+
+// out[i][j] = in[j][i] through a 64x64 LDS tile
+__global__ void __launch_bounds__(256) k_transpose(int rows, int cols, const double *in, double *out)
+{
+    __shared__ double t[64][65];
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    for (int r = ly; r < 64; r += 4)
+        if (r0 + r < rows && c0 + lx < cols) t[r][lx] = in[(size_t)(r0 + r) * cols + c0 + lx];
+    __syncthreads();
+    for (int c = ly; c < 64; c += 4)
+        if (c0 + c < cols && r0 + lx < rows) out[(size_t)(c0 + c) * rows + r0 + lx] = t[lx][c];
+}
+
+// partial sums of x . (wa a + wb b), compensated, fixed order
+__global__ void __launch_bounds__(256) k_dot(const double *x, const double *a, const double *b, double wa, double wb,
+                                             size_t n, double *partials)
+{
+    __shared__ double ss[256], sc[256];
+    double s = 0.0, c = 0.0;
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
+        double v = wa * a[k];
+        if (b != nullptr) v += wb * b[k];
+        const double p = x[k] * v;
+        const double t = s + p;
+        c += fabs(s) >= fabs(p) ? (s - t) + p : (p - t) + s;
+        s = t;
+    }
+    ss[threadIdx.x] = s;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double p = ss[threadIdx.x + w], q = ss[threadIdx.x];
+            const double t = q + p;
+            sc[threadIdx.x] += sc[threadIdx.x + w] + (fabs(q) >= fabs(p) ? (q - t) + p : (p - t) + q);
+            ss[threadIdx.x] = t;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = ss[0];
+        partials[2 * blockIdx.x + 1] = sc[0];
+    }
+}
+
+// random diagonally dominant test systems for the autotuner
+__global__ void k_fill_test(size_t n, double *bands, double *rhs)
+{
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
+        unsigned long long z = k * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const double r = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+        bands[k] = 0.1 * r;
+        bands[n + k] = -0.4 * r;
+        bands[2 * n + k] = 2.0 + r;
+        bands[3 * n + k] = -0.3 * r;
+        bands[4 * n + k] = 0.2 * r;
+        rhs[k] = r - 0.5;
+    }
+}
+
+} // namespace tf
+
+// =========================================================================================
+// host
+// =========================================================================================
+namespace {
+
+tf_status afail(tf_status s, const std::string &msg)
+{
+    tf_detail::set_error(msg);
+    return s;
+}
+
+#define TF_AHIP(call)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return afail(TF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+enum Variant { V_PARTITIONED = 0, V_THOMAS = 1 };
+const char *kVariantNames[] = {"partitioned", "thomas"};
+
+struct TuneTable {
+    std::mutex mu;
+    std::map<std::pair<int, int>, int> best; // (length, batch) -> variant
+};
+TuneTable &tune_table()
+{
+    static TuneTable t;
+    return t;
+}
+
+// variant for a batch of `nl` lines of length `np`: the autotuned entry with the
+// nearest (log-distance) key, else a heuristic (one lane per line only pays when the
+// lines alone fill the GPU)
+int pick_variant(int np, int nl)
+{
+    TuneTable &t = tune_table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    double best_d = 1e30;
+    int v = -1;
+    for (auto &kv : t.best) {
+        const double d = std::fabs(std::log((double)kv.first.first / np)) + std::fabs(std::log((double)kv.first.second / nl));
+        if (d < best_d) { best_d = d; v = kv.second; }
+    }
+    if (v >= 0 && best_d < 0.7) return v;
+    return nl >= 65536 ? V_THOMAS : V_PARTITIONED;
+}
+
+struct Scratch {
+    double *rel = nullptr, *ext = nullptr, *chain = nullptr, *work = nullptr;
+};
+
+tf_status sb_solve(int variant, bool trans, int mode, int nl, int np, const double *bands, const double *rhs,
+                   double *out, unsigned long long *red, const Scratch &S, hipStream_t s)
+{
+    tf::SBParams P{nl, np, bands, rhs, out, S.rel, S.ext, red};
+    if (variant == V_THOMAS) {
+        const dim3 g((nl + 63) / 64), b(64);
+        if (!trans && mode == 0) tf::k_sb_thomas<false, 0><<<g, b, 0, s>>>(P, S.work);
+        else if (!trans) tf::k_sb_thomas<false, 1><<<g, b, 0, s>>>(P, S.work);
+        else if (mode == 0) tf::k_sb_thomas<true, 0><<<g, b, 0, s>>>(P, S.work);
+        else tf::k_sb_thomas<true, 1><<<g, b, 0, s>>>(P, S.work);
+        TF_AHIP(hipGetLastError());
+        return TF_OK;
+    }
+    const int ntile = ((nl + 63) / 64) * tf::seg_count(np);
+    const dim3 g(ntile), b(tf::BLOCK);
+    if (trans) tf::k_sb_pass<false, true, 0><<<g, b, 0, s>>>(P);
+    else tf::k_sb_pass<false, false, 0><<<g, b, 0, s>>>(P);
+    TF_AHIP(hipGetLastError());
+    tf::ChainParams C{nl, tf::seg_count(np), S.rel, S.chain, S.ext};
+    TF_AHIP(tf::launch_chain(C, s));
+    if (trans && mode == 0) tf::k_sb_pass<true, true, 0><<<g, b, 0, s>>>(P);
+    else if (trans) tf::k_sb_pass<true, true, 1><<<g, b, 0, s>>>(P);
+    else if (mode == 0) tf::k_sb_pass<true, false, 0><<<g, b, 0, s>>>(P);
+    else tf::k_sb_pass<true, false, 1><<<g, b, 0, s>>>(P);
+    TF_AHIP(hipGetLastError());
+    return TF_OK;
+}
+
+struct AdjBuffers {
+    int nx = 0, ny = 0;
+    double *bx = nullptr, *by = nullptr, *mu = nullptr, *r = nullptr, *rT = nullptr, *y = nullptr, *yT = nullptr;
+    double *xi = nullptr, *loc = nullptr, *dk1 = nullptr, *dk0 = nullptr, *work = nullptr, *part = nullptr;
+    double *hpart = nullptr;
+    unsigned long long *red = nullptr, *hred = nullptr;
+};
+
+std::mutex g_adj_mu;
+std::map<const tf_grid *, AdjBuffers> g_adj;
+
+void free_adj(AdjBuffers &b)
+{
+    double *ps[] = {b.bx, b.by, b.mu, b.r, b.rT, b.y, b.yT, b.xi, b.loc, b.dk1, b.dk0, b.work, b.part};
+    for (double *p : ps) (void)hipFree(p);
+    (void)hipFree(b.red);
+    if (b.hpart) (void)hipHostFree(b.hpart);
+    if (b.hred) (void)hipHostFree(b.hred);
+    b = AdjBuffers{};
+}
+
+tf_status get_adj(const tf_grid *g, int nx, int ny, AdjBuffers **out)
+{
+    std::lock_guard<std::mutex> lk(g_adj_mu);
+    AdjBuffers &b = g_adj[g];
+    if (b.nx == nx && b.ny == ny && b.bx) {
+        *out = &b;
+        return TF_OK;
+    }
+    free_adj(b);
+    const size_t N = (size_t)nx * ny;
+    bool ok = hipMalloc(&b.bx, 5 * N * sizeof(double)) == hipSuccess && hipMalloc(&b.by, 5 * N * sizeof(double)) == hipSuccess
+              && hipMalloc(&b.mu, N * sizeof(double)) == hipSuccess && hipMalloc(&b.r, N * sizeof(double)) == hipSuccess
+              && hipMalloc(&b.rT, N * sizeof(double)) == hipSuccess && hipMalloc(&b.y, N * sizeof(double)) == hipSuccess
+              && hipMalloc(&b.yT, N * sizeof(double)) == hipSuccess && hipMalloc(&b.xi, N * sizeof(double)) == hipSuccess
+              && hipMalloc(&b.loc, N * sizeof(double)) == hipSuccess && hipMalloc(&b.dk1, N * sizeof(double)) == hipSuccess
+              && hipMalloc(&b.dk0, N * sizeof(double)) == hipSuccess
+              && hipMalloc(&b.work, 3 * N * sizeof(double)) == hipSuccess
+              && hipMalloc(&b.part, 2 * 4096 * sizeof(double)) == hipSuccess
+              && hipMalloc(&b.red, 8 * sizeof(unsigned long long)) == hipSuccess
+              && hipHostMalloc(&b.hpart, 2 * 4096 * sizeof(double), hipHostMallocDefault) == hipSuccess
+              && hipHostMalloc(&b.hred, 8 * sizeof(unsigned long long), hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_adj(b);
+        return afail(TF_ENOMEM, "adjoint scratch allocation failed");
+    }
+    b.nx = nx;
+    b.ny = ny;
+    *out = &b;
+    return TF_OK;
+}
+
+tf_status jdt(const tf_detail::GridView &v, const double *u, const double *mu, const double *lam, double a, double b,
+              double gmul, double *out, AdjBuffers &B)
+{
+    const double ids = 1.0 / v.ds, ids2 = ids * ids;
+    const dim3 grid((v.nx + 63) / 64, (v.ny + 3) / 4), blk(256);
+    if (v.M.p32) tf::k_jdt_xi<true><<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids, ids2, v.M, u, mu, B.xi, B.loc);
+    else tf::k_jdt_xi<false><<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids, ids2, v.M, u, mu, B.xi, B.loc);
+    TF_AHIP(hipGetLastError());
+    tf::k_jdt_out<<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids2, B.xi, B.loc, lam, mu, a, b, gmul, out);
+    TF_AHIP(hipGetLastError());
+    return TF_OK;
+}
+
+tf_status transpose(int rows, int cols, const double *in, double *out, hipStream_t s)
+{
+    tf::k_transpose<<<dim3((cols + 63) / 64, (rows + 63) / 64), dim3(256), 0, s>>>(rows, cols, in, out);
+    TF_AHIP(hipGetLastError());
+    return TF_OK;
+}
+
+tf_status dot(const double *x, const double *a, const double *b, double wa, double wb, size_t n, AdjBuffers &B,
+              hipStream_t s, double *res)
+{
+    size_t nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    tf::k_dot<<<dim3((unsigned)nb), dim3(256), 0, s>>>(x, a, b, wa, wb, n, B.part);
+    TF_AHIP(hipGetLastError());
+    TF_AHIP(hipMemcpyAsync(B.hpart, B.part, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    TF_AHIP(hipStreamSynchronize(s));
+    double sum = 0.0, c = 0.0;
+    for (size_t k = 0; k < nb; ++k) {
+        const double p = B.hpart[2 * k], t = sum + p;
+        c += (std::fabs(sum) >= std::fabs(p) ? (sum - t) + p : (p - t) + sum) + B.hpart[2 * k + 1];
+        sum = t;
+    }
+    *res = sum + c;
+    return TF_OK;
+}
+
+double bits_to_double(unsigned long long x)
+{
+    double d;
+    std::memcpy(&d, &x, sizeof d);
+    return d;
+}
+
+std::string arch_name()
+{
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string n = p.gcnArchName;
+    const size_t c = n.find(':');
+    return c == std::string::npos ? n : n.substr(0, c);
+}
+
+} // namespace
+
+namespace tf_detail {
+void release_adjoint(const tf_grid *g)
+{
+    std::lock_guard<std::mutex> lk(g_adj_mu);
+    auto it = g_adj.find(g);
+    if (it != g_adj.end()) {
+        free_adj(it->second);
+        g_adj.erase(it);
+    }
+}
+} // namespace tf_detail
+
+extern "C" {
+
+tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, double dt, double *lambda_inout,
+                          double *dL_dkappa_accum, double tol, int max_iter, int *iters_out)
+{
+    tf_detail::GridView v;
+    if (g == nullptr || h_n == nullptr || h_np1 == nullptr || lambda_inout == nullptr)
+        return afail(TF_EINVAL, "NULL argument");
+    if (!tf_detail::grid_view(g, &v)) return afail(TF_ESTATE, "model not set");
+    if (!(dt > 0.0) || !(tol > 0.0) || max_iter < 1) return afail(TF_EINVAL, "need dt > 0, tol > 0, max_iter >= 1");
+    AdjBuffers *Bp;
+    tf_status st = get_adj(g, v.nx, v.ny, &Bp);
+    if (st != TF_OK) return st;
+    AdjBuffers &B = *Bp;
+    const int nx = v.nx, ny = v.ny;
+    const size_t N = (size_t)nx * ny;
+    const double c = v.theta * dt;
+    const double ids = 1.0 / v.ds, ids2 = ids * ids;
+    const double k1 = c / v.ds, k3 = c / (v.ds * v.ds * v.ds * v.ds);
+    hipStream_t s = v.stream;
+    // bands of I + c J_x (stored [i][j]) and I + c J_y (stored [j][i]) at u^{n+1}
+    {
+        const dim3 gy((nx + 63) / 64, (ny + 3) / 4), gx((ny + 63) / 64, (nx + 3) / 4), blk(256);
+        if (v.M.p32) {
+            tf::k_bands_store<0, true><<<gy, blk, 0, s>>>(nx, ny, ids, ids2, k1, k3, v.M, h_np1, B.by);
+            tf::k_bands_store<1, true><<<gx, blk, 0, s>>>(nx, ny, ids, ids2, k1, k3, v.M, h_np1, B.bx);
+        } else {
+            tf::k_bands_store<0, false><<<gy, blk, 0, s>>>(nx, ny, ids, ids2, k1, k3, v.M, h_np1, B.by);
+            tf::k_bands_store<1, false><<<gx, blk, 0, s>>>(nx, ny, ids, ids2, k1, k3, v.M, h_np1, B.bx);
+        }
+        TF_AHIP(hipGetLastError());
+    }
+    Scratch S{v.rel, v.ext, v.chain, B.work};
+    const int vx = pick_variant(nx, ny), vy = pick_variant(ny, nx);
+    TF_AHIP(hipMemsetAsync(B.mu, 0, N * sizeof(double), s));
+    int it;
+    bool conv = false;
+    for (it = 1; it <= max_iter; ++it) {
+        // r = lambda - (I + c J^T) mu
+        if ((st = jdt(v, h_np1, B.mu, lambda_inout, 1.0, -1.0, -c, B.r, B)) != TF_OK) return st;
+        if ((st = transpose(ny, nx, B.r, B.rT, s)) != TF_OK) return st;
+        // (I + c J_x)^-T: rows as lines (transposed layout [i][j])
+        if ((st = sb_solve(vx, true, 0, ny, nx, B.bx, B.rT, B.yT, nullptr, S, s)) != TF_OK) return st;
+        if ((st = transpose(nx, ny, B.yT, B.y, s)) != TF_OK) return st;
+        // (I + c J_y)^-T: columns as lines; mu += z with max|z|, max|mu|
+        TF_AHIP(hipMemsetAsync(B.red, 0, 2 * sizeof(unsigned long long), s));
+        if ((st = sb_solve(vy, true, 1, nx, ny, B.by, B.y, B.mu, B.red, S, s)) != TF_OK) return st;
+        TF_AHIP(hipMemcpyAsync(B.hred, B.red, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        TF_AHIP(hipStreamSynchronize(s));
+        const double zmax = bits_to_double(B.hred[0]), mmax = bits_to_double(B.hred[1]);
+        if (!(zmax == zmax) || !(mmax == mmax)) return afail(TF_ENONPOS, "adjoint iteration produced NaN");
+        if (zmax <= tol * mmax) {
+            conv = true;
+            break;
+        }
+    }
+    if (iters_out) *iters_out = conv ? it : max_iter;
+    if (!conv) return afail(TF_ENOCONV, "adjoint Richardson iteration did not converge");
+    // kappa gradient: dL/dkappa -= dt mu . [theta dD/dk(u^{n+1}) + (1 - theta) dD/dk(u^n)]
+    if (dL_dkappa_accum != nullptr) {
+        tf::Model Mk = v.M; // f1 with kappa = 1, f0 dropped
+        Mk.kappa = 1.0;
+        Mk.Cn = v.M.Cn / (v.M.kappa != 0.0 ? v.M.kappa : 1.0);
+        Mk.Cm = v.M.Cm / (v.M.kappa != 0.0 ? v.M.kappa : 1.0);
+        Mk.Dn = v.M.Dn / (v.M.kappa != 0.0 ? v.M.kappa : 1.0);
+        Mk.Dm = v.M.Dm / (v.M.kappa != 0.0 ? v.M.kappa : 1.0);
+        if (v.M.kappa == 0.0) {
+            const double n = v.M.n, m = v.M.m, b = v.M.b;
+            Mk.Cn = n * std::pow(b, n); Mk.Cm = m * std::pow(b, m);
+            Mk.Dn = n * (n - 2.0) * std::pow(b, n); Mk.Dm = m * (m - 2.0) * std::pow(b, m);
+        }
+        TF_AHIP(tf::launch_flux_divergence_f1(nx, ny, ids, ids2, Mk, h_np1, B.dk1, s));
+        if (v.theta < 1.0) TF_AHIP(tf::launch_flux_divergence_f1(nx, ny, ids, ids2, Mk, h_n, B.dk0, s));
+        double d;
+        if ((st = dot(B.mu, B.dk1, v.theta < 1.0 ? B.dk0 : nullptr, v.theta, 1.0 - v.theta, N, B, s, &d)) != TF_OK)
+            return st;
+        *dL_dkappa_accum -= dt * d;
+    }
+    // lambda^n = mu - (1 - theta) dt J_D(u^n)^T mu
+    if (v.theta < 1.0) {
+        if ((st = jdt(v, h_n, B.mu, nullptr, 0.0, 1.0, -(1.0 - v.theta) * dt, lambda_inout, B)) != TF_OK) return st;
+    } else {
+        TF_AHIP(hipMemcpyAsync(lambda_inout, B.mu, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    TF_AHIP(hipStreamSynchronize(s));
+    return TF_OK;
+}
+
+tf_status tf_jacobian_apply_t(tf_grid *g, const double *u, const double *mu, double *out)
+{
+    tf_detail::GridView v;
+    if (g == nullptr || u == nullptr || mu == nullptr || out == nullptr) return afail(TF_EINVAL, "NULL argument");
+    if (!tf_detail::grid_view(g, &v)) return afail(TF_ESTATE, "model not set");
+    AdjBuffers *Bp;
+    tf_status st = get_adj(g, v.nx, v.ny, &Bp);
+    if (st != TF_OK) return st;
+    if ((st = jdt(v, u, mu, nullptr, 0.0, 0.0, 1.0, out, *Bp)) != TF_OK) return st;
+    TF_AHIP(hipStreamSynchronize(v.stream));
+    return TF_OK;
+}
+
+tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *rhs, double *x, int transposed,
+                         int variant, void *stream)
+{
+    if (nlines < 1 || n < 2 || bands == nullptr || rhs == nullptr || x == nullptr || variant < -1 || variant > 1)
+        return afail(TF_EINVAL, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t recs = (size_t)tf::seg_count(n) * nlines;
+    Scratch S;
+    bool ok = hipMalloc(&S.rel, recs * tf::NREL * sizeof(double)) == hipSuccess
+              && hipMalloc(&S.ext, recs * tf::NEXT * sizeof(double)) == hipSuccess
+              && hipMalloc(&S.chain, recs * tf::NCHAIN * sizeof(double)) == hipSuccess
+              && hipMalloc(&S.work, 3 * (size_t)n * nlines * sizeof(double)) == hipSuccess;
+    tf_status st = TF_OK;
+    if (!ok) st = afail(TF_ENOMEM, "scratch allocation failed");
+    if (st == TF_OK) {
+        const int v = variant < 0 ? pick_variant(n, nlines) : variant;
+        st = sb_solve(v, transposed != 0, 0, nlines, n, bands, rhs, x, nullptr, S, s);
+        if (st == TF_OK && hipStreamSynchronize(s) != hipSuccess) st = afail(TF_EDEVICE, "synchronize failed");
+    }
+    (void)hipFree(S.rel);
+    (void)hipFree(S.ext);
+    (void)hipFree(S.chain);
+    (void)hipFree(S.work);
+    return st;
+}
+
+tf_status tf_autotune(int length, int batch, const char *cache_path)
+{
+    if (length < 2 || batch < 1) return afail(TF_EINVAL, "need length >= 2 and batch >= 1");
+    const size_t N = (size_t)length * batch;
+    double *bands = nullptr, *rhs = nullptr, *x = nullptr;
+    Scratch S;
+    const size_t recs = (size_t)tf::seg_count(length) * batch;
+    hipStream_t s = nullptr;
+    bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess
+              && hipMalloc(&bands, 5 * N * sizeof(double)) == hipSuccess && hipMalloc(&rhs, N * sizeof(double)) == hipSuccess
+              && hipMalloc(&x, N * sizeof(double)) == hipSuccess
+              && hipMalloc(&S.rel, recs * tf::NREL * sizeof(double)) == hipSuccess
+              && hipMalloc(&S.ext, recs * tf::NEXT * sizeof(double)) == hipSuccess
+              && hipMalloc(&S.chain, recs * tf::NCHAIN * sizeof(double)) == hipSuccess
+              && hipMalloc(&S.work, 3 * N * sizeof(double)) == hipSuccess;
+    tf_status st = ok ? TF_OK : afail(TF_ENOMEM, "autotune allocation failed");
+    double ms[2] = {0.0, 0.0};
+    if (st == TF_OK) {
+        tf::k_fill_test<<<dim3(1024), dim3(256), 0, s>>>(N, bands, rhs);
+        hipEvent_t a, b;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        for (int v = 0; v < 2 && st == TF_OK; ++v) {
+            std::vector<float> t;
+            for (int r = 0; r < 6 && st == TF_OK; ++r) {
+                (void)hipEventRecord(a, s);
+                st = sb_solve(v, false, 0, batch, length, bands, rhs, x, nullptr, S, s);
+                (void)hipEventRecord(b, s);
+                (void)hipEventSynchronize(b);
+                float e = 0.0f;
+                (void)hipEventElapsedTime(&e, a, b);
+                if (r > 0) t.push_back(e); // first run is a warm-up
+            }
+            std::sort(t.begin(), t.end());
+            ms[v] = t.empty() ? 1e30 : t[t.size() / 2];
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    (void)hipFree(bands);
+    (void)hipFree(rhs);
+    (void)hipFree(x);
+    (void)hipFree(S.rel);
+    (void)hipFree(S.ext);
+    (void)hipFree(S.chain);
+    (void)hipFree(S.work);
+    if (s) (void)hipStreamDestroy(s);
+    if (st != TF_OK) return st;
+    const int best = ms[0] <= ms[1] ? V_PARTITIONED : V_THOMAS;
+    {
+        TuneTable &t = tune_table();
+        std::lock_guard<std::mutex> lk(t.mu);
+        t.best[{length, batch}] = best;
+    }
+    if (cache_path != nullptr && cache_path[0] != '\0') {
+        // one JSON object per line: {"arch", "length", "batch", "variant", "ms": {...}}
+        std::ofstream f(cache_path, std::ios::app);
+        if (!f) return afail(TF_EINVAL, std::string("cannot write ") + cache_path);
+        char line[512];
+        std::snprintf(line, sizeof line,
+                      "{\"arch\": \"%s\", \"length\": %d, \"batch\": %d, \"variant\": \"%s\", \"ms\": {\"%s\": %.6f, "
+                      "\"%s\": %.6f}}\n",
+                      arch_name().c_str(), length, batch, kVariantNames[best], kVariantNames[0], ms[0],
+                      kVariantNames[1], ms[1]);
+        f << line;
+    }
+    return TF_OK;
+}
+
+tf_status tf_autotune_load(const char *cache_path)
+{
+    if (cache_path == nullptr) return afail(TF_EINVAL, "NULL path");
+    std::ifstream f(cache_path);
+    if (!f) return afail(TF_EINVAL, std::string("cannot read ") + cache_path);
+    const std::string arch = arch_name();
+    std::string line;
+    int loaded = 0;
+    TuneTable &t = tune_table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    while (std::getline(f, line)) {
+        auto field = [&](const char *key) -> std::string {
+            const std::string k = std::string("\"") + key + "\": ";
+            const size_t p = line.find(k);
+            if (p == std::string::npos) return "";
+            size_t q = p + k.size();
+            if (line[q] == '"') {
+                const size_t e = line.find('"', q + 1);
+                return line.substr(q + 1, e - q - 1);
+            }
+            size_t e = q;
+            while (e < line.size() && (std::isdigit((unsigned char)line[e]) || line[e] == '-')) ++e;
+            return line.substr(q, e - q);
+        };
+        if (field("arch") != arch) continue;
+        const std::string L = field("length"), Bt = field("batch"), V = field("variant");
+        if (L.empty() || Bt.empty()) continue;
+        t.best[{std::stoi(L), std::stoi(Bt)}] = V == "thomas" ? V_THOMAS : V_PARTITIONED;
+        ++loaded;
+    }
+    return loaded > 0 ? TF_OK : afail(TF_EINVAL, "no entries for this GPU architecture in the cache");
+}
+
+int tf_autotune_choice(int length, int batch) { return pick_variant(length, batch); }
+
+} // extern "C"

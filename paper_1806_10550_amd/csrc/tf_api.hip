@@ -324,6 +324,23 @@ bool is_int(double x) { return std::isfinite(x) && std::floor(x) == x; }
 
 } // namespace
 
+namespace tf_detail {
+bool grid_view(const tf_grid *g, GridView *v)
+{
+    if (g == nullptr || !g->model_set) return false;
+    v->nx = g->nx;
+    v->ny = g->ny;
+    v->ds = g->ds;
+    v->theta = g->S.theta;
+    v->M = g->M;
+    v->stream = g->stream;
+    v->rel = g->rel;
+    v->ext = g->ext;
+    v->chain = g->chain;
+    return true;
+}
+} // namespace tf_detail
+
 extern "C" {
 
 const char *tf_last_error(void) { return g_err.c_str(); }
@@ -376,7 +393,8 @@ tf_status tf_create(int nx, int ny, double ds, void *stream, tf_grid **out)
 tf_status tf_destroy(tf_grid *g)
 {
     if (g == nullptr) return TF_OK;
-    if (g->stream != nullptr || true) (void)hipStreamSynchronize(g->stream);
+    (void)hipStreamSynchronize(g->stream);
+    tf_detail::release_adjoint(g);
     for (auto &e : g->ev) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);

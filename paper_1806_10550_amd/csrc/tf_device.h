@@ -1,0 +1,310 @@
+// Device helpers shared by the forward sweeps (tf_kernels.hip) and the adjoint /
+// stored-band solvers (tf_adjoint.hip): model coefficients, cell and face quantities,
+// the reciprocal, ghost reflection, and the interface-chain algebra.
+#pragma once
+
+#include "tf_internal.h"
+
+namespace tf {
+
+// Reciprocal from the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r); accurate to about one ulp for normal x.
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+__device__ __forceinline__ double ipow(double r, double h, int k)
+{
+    const double base = k >= 0 ? r : h;
+    const int e = k >= 0 ? k : -k;
+    double acc = 1.0;
+    for (int i = 0; i < e; ++i) acc *= base;
+    return acc;
+}
+
+// f0 = h^3, f0' = 3h^2, f1 = kappa h^3 f'(h), f1' (see Model).
+template <bool P32>
+__device__ __forceinline__ void model_coefs(const Model &M, double u, double &f0, double &f1,
+                                            double &f0p, double &f1p)
+{
+    const double r = rcp(u);
+    const double u2 = u * u;
+    f0 = u2 * u;
+    f0p = 3.0 * u2;
+    if (P32) {
+        f1 = M.Cm - M.Cn * r;
+        f1p = M.Dn * (r * r);
+    } else {
+        f1 = M.Cm * ipow(r, u, M.m - 2) - M.Cn * ipow(r, u, M.n - 2);
+        f1p = M.Dn * ipow(r, u, M.n - 1) - M.Dm * ipow(r, u, M.m - 1);
+    }
+}
+
+struct Cell {
+    double u, lap, f0, f1, f0p, f1p; // f0p, f1p hold f0'/2 and f1'/2
+};
+
+// Even reflection across the boundary faces (no-flux ghosts), clamped so that a
+// ragged tile never reads outside the grid.
+__device__ __forceinline__ int crefl(int k, int n)
+{
+    if (k < 0) k = -1 - k;
+    if (k >= n) k = 2 * n - 1 - k;
+    return k < 0 ? 0 : (k >= n ? n - 1 : k);
+}
+
+// LDS u tile: (line l, position p) in tile-local coordinates, -HALO <= l, p < TILE+HALO.
+// DIR 0 (y sweep): lines are grid columns (x), positions rows (y).
+// DIR 1 (x sweep): lines are grid rows (y), positions columns (x).
+template <int DIR>
+__device__ __forceinline__ double uat(const double *sU, int l, int p)
+{
+    return DIR == 0 ? sU[(p + HALO) * UPITCH + (l + HALO)] : sU[(l + HALO) * UPITCH + (p + HALO)];
+}
+
+template <int DIR, bool P32>
+__device__ __forceinline__ Cell cell_at(const double *sU, const Model &M, double ids2, int l, int p)
+{
+    Cell c;
+    c.u = uat<DIR>(sU, l, p);
+    double xp, xm, yp, ym;
+    if (DIR == 0) {
+        xp = uat<DIR>(sU, l + 1, p); xm = uat<DIR>(sU, l - 1, p);
+        yp = uat<DIR>(sU, l, p + 1); ym = uat<DIR>(sU, l, p - 1);
+    } else {
+        xp = uat<DIR>(sU, l, p + 1); xm = uat<DIR>(sU, l, p - 1);
+        yp = uat<DIR>(sU, l + 1, p); ym = uat<DIR>(sU, l - 1, p);
+    }
+    c.lap = (xp + xm + yp + ym - 4.0 * c.u) * ids2;
+    model_coefs<P32>(M, c.u, c.f0, c.f1, c.f0p, c.f1p);
+    c.f0p *= 0.5; // the bands use f0'/2 and f1'/2
+    c.f1p *= 0.5;
+    return c;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous run
+// of tiles so that neighbouring tiles share halos in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int q = n >> 3, r = n & 7;
+    const int x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// ---- 2x2 / 2x5 helpers for the interface chain --------------------------------------
+struct M2 { double a, b, c, d; }; // [[a b] [c d]]
+
+__device__ __forceinline__ M2 mul(const M2 &x, const M2 &y)
+{
+    return {x.a * y.a + x.b * y.c, x.a * y.b + x.b * y.d, x.c * y.a + x.d * y.c, x.c * y.b + x.d * y.d};
+}
+__device__ __forceinline__ M2 inv_i_minus(const M2 &x) // (I - x)^-1
+{
+    const double a = 1.0 - x.a, b = -x.b, c = -x.c, d = 1.0 - x.d;
+    const double r = rcp(a * d - b * c);
+    return {d * r, -b * r, -c * r, a * r};
+}
+
+// Relation record of one segment for one line: with (l1, l2) the two cells before the
+// segment and (r1, r2) the two cells after it,
+//   top pair    T[i] = T[i][0] + T[i][1] l1 + T[i][2] l2 + T[i][3] r1 + T[i][4] r2
+//   bottom pair B[i] = ...
+// stored as NREL doubles: T[0][0..4], T[1][0..4], B[0][0..4], B[1][0..4].
+struct Rel {
+    double T[2][5], B[2][5];
+};
+
+// Relation record q of this lane from the LDS exchange area.
+__device__ __forceinline__ void load_rel(const double *sB, int q, int lane, Rel &S)
+{
+    const double *src = sB + (size_t)q * NREL * 64 + lane;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            S.T[i][j] = src[(i * 5 + j) * 64];
+            S.B[i][j] = src[(10 + i * 5 + j) * 64];
+        }
+}
+
+// Interface chain over the Q sub-segments of a tile (forward block elimination):
+// with B_{q-1} = bt_{q-1} + M_{q-1} T_q from the previous step, sub-segment q gives
+//   T_q = tau_q + N_q T_{q+1},  tau_q = K (t_q + Tl_q bt_{q-1}),  N_q = K Tr_q,
+//   K = (I - Tl_q M_{q-1})^-1,
+//   B_q = bt_q + M_q T_{q+1},   bt_q = b_q + Bl_q (bt_{q-1} + M_{q-1} tau_q),
+//   M_q = Bl_q M_{q-1} N_q + Br_q.
+// The recurrences below carry only what later steps need, so T_0 (and the boundary
+// values a wave needs) follow from forward accumulation: T_0 = sum_q N_0..N_{q-1} tau_q
+// + N_0..N_{Q-1} T_Q.
+
+// Symbolic version: quantities are affine forms over (1, l1, l2, r1, r2), the tile's
+// outer boundary values. Returns the tile's relation record (T_0, B_{Q-1}).
+__device__ __forceinline__ void chain_symbolic(const double *sB, int lane, int Q, Rel &out)
+{
+    double bt[2][5], acc[2][5];
+    M2 Mm = {0, 0, 0, 0}, P = {1, 0, 0, 1};
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) { bt[i][j] = 0.0; acc[i][j] = 0.0; }
+#pragma unroll
+    for (int q = 0; q < NSUB; ++q) {
+        if (q >= Q) break;
+        Rel S;
+        load_rel(sB, q, lane, S);
+        const M2 Tl = {S.T[0][1], S.T[0][2], S.T[1][1], S.T[1][2]};
+        const M2 Tr = {S.T[0][3], S.T[0][4], S.T[1][3], S.T[1][4]};
+        const M2 Bl = {S.B[0][1], S.B[0][2], S.B[1][1], S.B[1][2]};
+        const M2 Br = {S.B[0][3], S.B[0][4], S.B[1][3], S.B[1][4]};
+        double tau[2][5];
+        M2 N;
+        if (q == 0) {
+            // B_{-1} is the outer pair (l1, l2)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                tau[i][0] = S.T[i][0]; tau[i][1] = S.T[i][1]; tau[i][2] = S.T[i][2]; tau[i][3] = 0.0; tau[i][4] = 0.0;
+                bt[i][0] = S.B[i][0]; bt[i][1] = S.B[i][1]; bt[i][2] = S.B[i][2]; bt[i][3] = 0.0; bt[i][4] = 0.0;
+            }
+            N = Tr;
+            Mm = Br;
+        } else {
+            const M2 K = inv_i_minus(mul(Tl, Mm));
+            N = mul(K, Tr);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                const double s0 = (j == 0 ? S.T[0][0] : 0.0) + Tl.a * bt[0][j] + Tl.b * bt[1][j];
+                const double s1 = (j == 0 ? S.T[1][0] : 0.0) + Tl.c * bt[0][j] + Tl.d * bt[1][j];
+                tau[0][j] = K.a * s0 + K.b * s1;
+                tau[1][j] = K.c * s0 + K.d * s1;
+                const double v0 = bt[0][j] + Mm.a * tau[0][j] + Mm.b * tau[1][j];
+                const double v1 = bt[1][j] + Mm.c * tau[0][j] + Mm.d * tau[1][j];
+                bt[0][j] = (j == 0 ? S.B[0][0] : 0.0) + Bl.a * v0 + Bl.b * v1;
+                bt[1][j] = (j == 0 ? S.B[1][0] : 0.0) + Bl.c * v0 + Bl.d * v1;
+            }
+            const M2 BM = mul(mul(Bl, Mm), N);
+            Mm = {BM.a + Br.a, BM.b + Br.b, BM.c + Br.c, BM.d + Br.d};
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            acc[0][j] += P.a * tau[0][j] + P.b * tau[1][j];
+            acc[1][j] += P.c * tau[0][j] + P.d * tau[1][j];
+        }
+        P = mul(P, N);
+    }
+    // T_Q is the outer right pair: the forms r1, r2
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            out.T[i][j] = acc[i][j];
+            out.B[i][j] = bt[i][j];
+        }
+    out.T[0][3] += P.a; out.T[0][4] += P.b; out.T[1][3] += P.c; out.T[1][4] += P.d;
+    out.B[0][3] += Mm.a; out.B[0][4] += Mm.b; out.B[1][3] += Mm.c; out.B[1][4] += Mm.d;
+}
+
+// Numeric version with the outer values known: returns the boundary values of
+// sub-segment w, lo = B_{w-1} (the outer l for w = 0) and hi = T_{w+1} (outer r for the
+// last sub-segment).
+__device__ __forceinline__ void chain_numeric(const double *sB, int lane, int Q, int w, double l1, double l2,
+                                              double r1, double r2, double &lo1, double &lo2, double &hi1,
+                                              double &hi2)
+{
+    double bt0 = 0.0, bt1 = 0.0;
+    M2 Mm = {0, 0, 0, 0};
+    double sbt0 = 0.0, sbt1 = 0.0, stau0 = 0.0, stau1 = 0.0; // bt_{w-1}, tau_w
+    M2 sM = {0, 0, 0, 0}, sN = {0, 0, 0, 0};                 // M_{w-1}, N_w
+    double acc0 = 0.0, acc1 = 0.0;
+    M2 P = {1, 0, 0, 1};
+#pragma unroll
+    for (int q = 0; q < NSUB; ++q) {
+        if (q >= Q) break;
+        Rel S;
+        load_rel(sB, q, lane, S);
+        const M2 Tl = {S.T[0][1], S.T[0][2], S.T[1][1], S.T[1][2]};
+        const M2 Tr = {S.T[0][3], S.T[0][4], S.T[1][3], S.T[1][4]};
+        const M2 Bl = {S.B[0][1], S.B[0][2], S.B[1][1], S.B[1][2]};
+        const M2 Br = {S.B[0][3], S.B[0][4], S.B[1][3], S.B[1][4]};
+        double tau0, tau1;
+        M2 N;
+        if (q == 0) {
+            tau0 = S.T[0][0] + Tl.a * l1 + Tl.b * l2;
+            tau1 = S.T[1][0] + Tl.c * l1 + Tl.d * l2;
+            N = Tr;
+            bt0 = S.B[0][0] + Bl.a * l1 + Bl.b * l2;
+            bt1 = S.B[1][0] + Bl.c * l1 + Bl.d * l2;
+            Mm = Br;
+        } else {
+            if (q == w) { sbt0 = bt0; sbt1 = bt1; sM = Mm; }
+            const M2 K = inv_i_minus(mul(Tl, Mm));
+            const double s0 = S.T[0][0] + Tl.a * bt0 + Tl.b * bt1;
+            const double s1 = S.T[1][0] + Tl.c * bt0 + Tl.d * bt1;
+            tau0 = K.a * s0 + K.b * s1;
+            tau1 = K.c * s0 + K.d * s1;
+            N = mul(K, Tr);
+            const double v0 = bt0 + Mm.a * tau0 + Mm.b * tau1;
+            const double v1 = bt1 + Mm.c * tau0 + Mm.d * tau1;
+            bt0 = S.B[0][0] + Bl.a * v0 + Bl.b * v1;
+            bt1 = S.B[1][0] + Bl.c * v0 + Bl.d * v1;
+            const M2 BM = mul(mul(Bl, Mm), N);
+            Mm = {BM.a + Br.a, BM.b + Br.b, BM.c + Br.c, BM.d + Br.d};
+        }
+        if (q == w) { stau0 = tau0; stau1 = tau1; sN = N; }
+        if (q > w) {
+            acc0 += P.a * tau0 + P.b * tau1;
+            acc1 += P.c * tau0 + P.d * tau1;
+            P = mul(P, N);
+        }
+    }
+    // T_{w+1} (the outer r when w is the last sub-segment)
+    hi1 = acc0 + P.a * r1 + P.b * r2;
+    hi2 = acc1 + P.c * r1 + P.d * r2;
+    if (w == 0) {
+        lo1 = l1;
+        lo2 = l2;
+    } else {
+        const double t0 = stau0 + sN.a * hi1 + sN.b * hi2;
+        const double t1 = stau1 + sN.c * hi1 + sN.d * hi2;
+        lo1 = sbt0 + sM.a * t0 + sM.b * t1;
+        lo2 = sbt1 + sM.c * t0 + sM.d * t1;
+    }
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ unsigned wave_or(unsigned v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
+
+struct FaceQ {
+    double kA, P, Q, F; // k3 A, k1 (f0'_L Lam + f1'_L Gam)/2 - k1 B/ds, the same with R and +B, flux
+};
+
+template <bool FLUX>
+__device__ __forceinline__ FaceQ face_q(const Cell &L, const Cell &R, bool interior, double ids, double k1,
+                                        double k3)
+{
+    FaceQ f;
+    const double A = 0.5 * (L.f0 + R.f0), B = 0.5 * (L.f1 + R.f1);
+    const double Lam = (R.lap - L.lap) * ids, Gam = (R.u - L.u) * ids;
+    const double Bi = B * ids;
+    f.kA = interior ? k3 * A : 0.0;
+    f.P = interior ? k1 * (L.f0p * Lam + L.f1p * Gam - Bi) : 0.0;
+    f.Q = interior ? k1 * (R.f0p * Lam + R.f1p * Gam + Bi) : 0.0;
+    f.F = (FLUX && interior) ? A * Lam + B * Gam : 0.0;
+    return f;
+}
+
+} // namespace tf

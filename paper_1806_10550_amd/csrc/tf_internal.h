@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 namespace tf {
 
@@ -108,6 +109,9 @@ struct EnsParams {
 enum ResultFlag { FLAG_NONPOS = 1, FLAG_NAN = 2 };
 
 // Launchers (tf_kernels.hip). Each returns the launch status.
+// out = D(u) evaluated with f0 = 0 (the f1 part only; with kappa = 1 this is dD/dkappa)
+hipError_t launch_flux_divergence_f1(int nx, int ny, double ids, double ids2, const Model &M, const double *u,
+                                     double *out, hipStream_t s);
 hipError_t launch_pass(int dir, bool solve, const PassParams &p, hipStream_t s);
 hipError_t launch_chain(const ChainParams &c, hipStream_t s);
 hipError_t launch_flux_divergence(int nx, int ny, double ids, double ids2, const Model &M,
@@ -124,3 +128,17 @@ hipError_t launch_ens_validate(const FilmDesc *desc, FilmState *st, int nfilms, 
 int mass_blocks(size_t n);
 
 } // namespace tf
+
+struct tf_grid;
+namespace tf_detail {
+struct GridView {
+    int nx, ny;
+    double ds, theta;
+    tf::Model M;
+    hipStream_t stream;
+    double *rel, *ext, *chain;
+};
+bool grid_view(const tf_grid *g, GridView *v);   // false if the model is not set
+void release_adjoint(const tf_grid *g);           // frees adjoint scratch of a grid
+void set_error(const std::string &msg);
+} // namespace tf_detail

@@ -81,6 +81,13 @@ def lib():
         L.tf_ensemble_bind.argtypes = [P, P]
         L.tf_ensemble_step.argtypes = [P, C.c_int, DP, IP, IP]
         L.tf_ensemble_film_info.argtypes = [P, C.c_int, C.POINTER(StepInfo)]
+        L.tf_adjoint_step.argtypes = [P, P, P, D, P, DP, D, C.c_int, IP]
+        L.tf_jacobian_apply_t.argtypes = [P, P, P, P]
+        L.tf_penta_solve.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, C.c_int, P]
+        L.tf_autotune.argtypes = [C.c_int, C.c_int, C.c_char_p]
+        L.tf_autotune_load.argtypes = [C.c_char_p]
+        L.tf_autotune_choice.argtypes = [C.c_int, C.c_int]
+        L.tf_autotune_choice.restype = C.c_int
         _lib = L
     return _lib
 
@@ -206,6 +213,19 @@ class Grid:
         _check(lib().tf_flux_divergence(self._h, _ptr(u), _ptr(out)))
         return out
 
+    def adjoint_step(self, h_n, h_np1, dt: float, lam, tol: float = 1e-13, max_iter: int = 2000):
+        """lam (device, in/out): lambda^{n+1} -> lambda^n. Returns (dL/dkappa contribution,
+        Richardson iterations)."""
+        g = C.c_double(0.0)
+        it = C.c_int(0)
+        _check(lib().tf_adjoint_step(self._h, _ptr(h_n), _ptr(h_np1), float(dt), _ptr(lam), C.byref(g),
+                                     float(tol), int(max_iter), C.byref(it)))
+        return g.value, it.value
+
+    def jacobian_apply_t(self, u, mu, out):
+        _check(lib().tf_jacobian_apply_t(self._h, _ptr(u), _ptr(mu), _ptr(out)))
+        return out
+
     def profile(self, on: bool):
         _check(lib().tf_profile(self._h, int(bool(on))))
 
@@ -281,3 +301,30 @@ class Ensemble:
         info = StepInfo()
         _check(lib().tf_ensemble_film_info(self._h, int(f), C.byref(info)))
         return info.as_dict()
+
+
+VARIANTS = {"auto": -1, "partitioned": 0, "thomas": 1}
+
+
+def penta_solve(bands, rhs, x, transposed=False, variant="auto", stream=None):
+    """Batched pentadiagonal solve on stored bands (tf_penta_solve). bands: (5, n, nlines)
+    float64 CUDA tensor, rhs and x: (n, nlines)."""
+    n, nl = rhs.shape
+    if tuple(bands.shape) != (5, n, nl) or tuple(x.shape) != (n, nl):
+        raise ValueError("bands must be (5, n, nlines) and rhs, x (n, nlines)")
+    _check(lib().tf_penta_solve(int(nl), int(n), _ptr(bands), _ptr(rhs), _ptr(x), int(bool(transposed)),
+                                VARIANTS[variant], _stream_ptr(stream)))
+    return x
+
+
+def autotune(length: int, batch: int, cache_path: str | None = None) -> str:
+    _check(lib().tf_autotune(int(length), int(batch), cache_path.encode() if cache_path else None))
+    return ["partitioned", "thomas"][lib().tf_autotune_choice(int(length), int(batch))]
+
+
+def autotune_load(cache_path: str) -> None:
+    _check(lib().tf_autotune_load(cache_path.encode()))
+
+
+def autotune_choice(length: int, batch: int) -> str:
+    return ["partitioned", "thomas"][lib().tf_autotune_choice(int(length), int(batch))]

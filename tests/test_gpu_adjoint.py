@@ -1,0 +1,167 @@
+"""GPU adjoint path: transposed Jacobian, stored-band pentadiagonal solves, one adjoint
+step and the checkpointed rollout gradient, against the CPU oracle and finite
+differences."""
+import json
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1806_10550_amd import synth
+from paper_1806_10550_amd.adjoint import rollout
+from paper_1806_10550_amd.lib import Grid, autotune, autotune_choice, autotune_load, penta_solve
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def grid(nx, ny, ds, theta=1.0, kappa=10.0, **kw):
+    g = Grid(nx, ny, ds)
+    g.set_model(kappa, 0.1, 3, 2)
+    g.set_scheme(theta=theta, **kw)
+    return g
+
+
+@pytest.mark.parametrize("nx,ny", [(9, 7), (70, 66), (130, 67)])
+def test_jacobian_transpose_matches_oracle(orc, nx, ny):
+    u = synth.noise_film(nx, ny, seed=nx + ny, amp=0.2)
+    mu = np.random.default_rng(nx).standard_normal((ny, nx))
+    ds = 0.8
+    g = grid(nx, ny, ds)
+    out = torch.empty((ny, nx), dtype=torch.float64, device=DEV)
+    g.jacobian_apply_t(gpu(u), gpu(mu), out)
+    ref = orc.jacobian_apply_t(orc.Model(), u, mu, ds)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def _bands(n, nl, seed, dominant=True):
+    rng = np.random.default_rng(seed)
+    b = rng.standard_normal((5, n, nl))
+    if dominant:
+        b[2] = 6.0 + rng.random((n, nl))
+    for p in range(n):
+        for o in range(5):
+            if not 0 <= p + o - 2 < n:
+                b[o, p, :] = 0.0
+    return b
+
+
+@pytest.mark.parametrize("n,nl", [(2, 3), (5, 7), (64, 64), (65, 130), (200, 33), (1000, 5)])
+@pytest.mark.parametrize("transposed", [False, True])
+@pytest.mark.parametrize("variant", ["partitioned", "thomas"])
+def test_penta_solve_matches_oracle(orc, n, nl, transposed, variant):
+    b = _bands(n, nl, seed=n * 7 + nl)
+    rhs = np.random.default_rng(n + nl).standard_normal((n, nl))
+    x = torch.empty((n, nl), dtype=torch.float64, device=DEV)
+    penta_solve(gpu(b), gpu(rhs), x, transposed=transposed, variant=variant)
+    got = x.cpu().numpy()
+    for l in range(nl):
+        band = np.ascontiguousarray(b[:, :, l])
+        if transposed:
+            band = orc.band_transpose(band)
+        ref = orc.band_solve(band, rhs[:, l])
+        assert np.max(np.abs(got[:, l] - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), l
+
+
+@pytest.mark.parametrize("variant", ["partitioned", "thomas"])
+def test_penta_solve_on_model_bands(orc, variant):
+    """Real (I + c J_x) systems of a noisy film (not diagonally dominant)."""
+    nx, ny = 300, 40
+    u = synth.noise_film(nx, ny, seed=5, amp=0.01)
+    M = orc.Model()
+    b = np.stack([orc.bands_x(M, u, 0.67347, 0.2, j) for j in range(ny)], axis=2)  # (5, nx, ny)
+    rhs = np.random.default_rng(1).standard_normal((nx, ny))
+    x = torch.empty((nx, ny), dtype=torch.float64, device=DEV)
+    penta_solve(gpu(b), gpu(rhs), x, variant=variant)
+    got = x.cpu().numpy()
+    for j in range(ny):
+        ref = orc.band_solve(np.ascontiguousarray(b[:, :, j]), rhs[:, j])
+        assert np.max(np.abs(got[:, j] - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_adjoint_step_matches_oracle(orc, theta):
+    nx, ny, ds, dt = 40, 30, 0.67347, 0.1
+    un = synth.noise_film(nx, ny, seed=2, amp=0.01)
+    M = orc.Model()
+    unp1, res = orc.step(M, orc.Scheme(theta=theta, tol=1e-14), un, ds, dt)
+    assert res.status == orc.OK
+    lam = np.random.default_rng(3).standard_normal((ny, nx))
+    ref, gk_ref, _ = orc.adjoint_step(M, un, unp1, lam, ds, dt, theta, tol=1e-14)
+    g = grid(nx, ny, ds, theta=theta)
+    lg = gpu(lam)
+    gk, it = g.adjoint_step(gpu(un), gpu(unp1), dt, lg, tol=1e-14)
+    got = lg.cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+    assert gk == pytest.approx(gk_ref, rel=1e-9)
+
+
+def _loss(h, target):
+    return 0.5 * torch.sum((h - target) ** 2)
+
+
+def test_rollout_gradient_matches_finite_differences():
+    """32 x 32 film, 10 backward-Euler steps (forward tol 1e-14): the checkpointed
+    adjoint gradient in p0 and kappa matches central differences."""
+    n, steps, dt = 32, 10, 0.1
+    ds = 16 * synth.lambda_m(10.0) / 512  # the 512^2 adjoint case's cell size
+    base = gpu(synth.noise_film(n, n, seed=4, amp=0.01))
+    target = gpu(synth.noise_film(n, n, seed=5, amp=0.01))
+    p0 = torch.zeros((n, n), dtype=torch.float64, device=DEV, requires_grad=True)
+    kap = torch.tensor(10.0, dtype=torch.float64, device=DEV, requires_grad=True)
+    h = rollout(p0, kap, base, steps, dt, ds, checkpoint_every=4, tol=1e-14, adj_tol=1e-14)
+    L = _loss(h, target)
+    L.backward()
+    d = gpu(np.random.default_rng(7).standard_normal((n, n)))
+    eps = 1e-5
+    with torch.no_grad():
+        Lp = _loss(rollout(p0 + eps * d, kap, base, steps, dt, ds, tol=1e-14), target).item()
+        Lm = _loss(rollout(p0 - eps * d, kap, base, steps, dt, ds, tol=1e-14), target).item()
+        fd = (Lp - Lm) / (2 * eps)
+        assert torch.sum(p0.grad * d).item() == pytest.approx(fd, rel=1e-6)
+        ek = 1e-5
+        Lp = _loss(rollout(p0, kap + ek, base, steps, dt, ds, tol=1e-14), target).item()
+        Lm = _loss(rollout(p0, kap - ek, base, steps, dt, ds, tol=1e-14), target).item()
+        assert kap.grad.item() == pytest.approx((Lp - Lm) / (2 * ek), rel=1e-6)
+
+
+def test_rollout_gradient_matches_oracle_adjoint(orc):
+    """Same rollout: GPU gradient vs the oracle's forward + adjoint chain, 1e-8 relative."""
+    n, steps, dt = 32, 10, 0.1
+    ds = 16 * synth.lambda_m(10.0) / 512
+    b_np = synth.noise_film(n, n, seed=4, amp=0.01)
+    t_np = synth.noise_film(n, n, seed=5, amp=0.01)
+    p0 = torch.zeros((n, n), dtype=torch.float64, device=DEV, requires_grad=True)
+    kap = torch.tensor(10.0, dtype=torch.float64, device=DEV, requires_grad=True)
+    h = rollout(p0, kap, gpu(b_np), steps, dt, ds, checkpoint_every=3, tol=1e-14, adj_tol=1e-14)
+    _loss(h, gpu(t_np)).backward()
+    M = orc.Model()
+    traj = [b_np]
+    u = b_np
+    for _ in range(steps):
+        u, res = orc.step(M, orc.Scheme(tol=1e-14), u, ds, dt)
+        traj.append(u)
+    lam = traj[-1] - t_np
+    gk = 0.0
+    for s in range(steps - 1, -1, -1):
+        lam, c, _ = orc.adjoint_step(M, traj[s], traj[s + 1], lam, ds, dt, 1.0, tol=1e-14)
+        gk += c
+    g = p0.grad.cpu().numpy()
+    assert np.max(np.abs(g - lam)) <= 1e-8 * np.max(np.abs(lam))
+    assert kap.grad.item() == pytest.approx(gk, rel=1e-8)
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    path = str(tmp_path / "tune.jsonl")
+    choice = autotune(512, 512, path)
+    assert choice in ("partitioned", "thomas")
+    rec = json.loads(open(path).read().strip().splitlines()[-1])
+    assert rec["length"] == 512 and rec["batch"] == 512 and rec["variant"] == choice
+    assert set(rec["ms"]) == {"partitioned", "thomas"} and all(math.isfinite(v) for v in rec["ms"].values())
+    autotune_load(path)
+    assert autotune_choice(512, 512) == choice
