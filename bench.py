@@ -141,14 +141,66 @@ def bench_ensemble(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args):
+    """512^2 film (L = 16 lambda_m), kappa = 10, backward Euler dt = 0.1 for `steps`
+    steps; loss 0.5 ||h(T) - h_target||^2 with h_target a forward run from another seed;
+    gradient in the initial perturbation and kappa by the checkpointed discrete adjoint
+    (h stored every 20 steps, steps in between recomputed). Reports the time of forward +
+    backward against the plain forward."""
+    import torch
+
+    from paper_1806_10550_amd import synth
+    from paper_1806_10550_amd.adjoint import rollout
+    from paper_1806_10550_amd.lib import Grid
+
+    cfg = synth.CONFIGS["adjoint512"]
+    n, dt, steps = cfg.n, cfg.dt, args.steps
+    dev = torch.device("cuda:0")
+    base = torch.from_numpy(synth.noise_film(n, n, cfg.seed, 1.0, 0.01)).to(dev)
+    tgt = torch.from_numpy(synth.noise_film(n, n, cfg.extra["target_seed"], 1.0, 0.01)).to(dev)
+    g = Grid(n, n, cfg.ds)
+    g.set_model(cfg.kappa, cfg.b, 3, 2)
+    g.set_scheme(theta=1.0, tol=cfg.tol, max_newton=5000)
+    g.bind(tgt)
+    g.advance(steps, dt)                      # target = forward run from seed 5
+    h = base.clone()
+    g.bind(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, log = g.advance(steps, dt, log=True)   # plain forward
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    fwd_iters = sum(x["total_iters"] for x in log)
+    p0 = torch.zeros_like(base, requires_grad=True)
+    kap = torch.tensor(cfg.kappa, dtype=torch.float64, device=dev, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hT = rollout(p0, kap, base, steps, dt, cfg.ds, checkpoint_every=cfg.extra["checkpoint_every"],
+                 tol=cfg.tol, adj_tol=1e-12)
+    loss = 0.5 * torch.sum((hT - tgt) ** 2)
+    loss.backward()
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    out = {"metric": "adjoint (forward + recompute + backward) time vs plain forward", "value": t_adj / t_fwd,
+           "unit": "ratio", "n_gpus": 1, "steps": steps, "higher_is_better": False, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"adjoint512: {n}x{n} film, L=16 lambda_m, kappa=10, backward Euler dt={dt}, "
+                                  f"{steps} steps, checkpoints every {cfg.extra['checkpoint_every']}, "
+                                  f"loss 0.5||h(T)-h_target||^2"},
+           "forward_s": t_fwd, "forward_plus_adjoint_s": t_adj, "forward_newton_iters": fwd_iters,
+           "loss": loss.item(), "grad_p0_norm": p0.grad.norm().item(), "grad_kappa": kap.grad.item()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="large8192")
-    ap.add_argument("--workload", default="single", choices=["single", "ensemble"],
-                    help="single: the 8192^2 film (default); ensemble: 256 ragged films")
+    ap.add_argument("--workload", default="single", choices=["single", "ensemble", "adjoint"],
+                    help="single: the 8192^2 film (default); ensemble: 256 ragged films; "
+                         "adjoint: 512^2 gradient by the checkpointed adjoint")
     ap.add_argument("--films", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -175,6 +227,9 @@ def main():
 
     if args.workload == "ensemble":
         bench_ensemble(args)
+        return
+    if args.workload == "adjoint":
+        bench_adjoint(args)
         return
 
     import torch

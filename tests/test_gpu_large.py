@@ -1,0 +1,87 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times.
+
+* 2048^2 spinodal and nucleation films (L = 64 lambda_m, adaptive dt from 0.1 with
+  K = 10): the first accepted steps, every cell, dt schedule and rejections.
+* 8192^2 film (L = 256 lambda_m, dt = 0.2): one full Newton iteration, every cell, and
+  the reduction record.
+* 2048^2 spinodal over many steps on the GPU alone: mass to 1e-12, positivity.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1806_10550_amd import synth
+from paper_1806_10550_amd.lib import Grid
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+ADAPT = dict(tol=1e-10, max_newton=10, adaptive=1, dt_min=1e-6, dt_max=1.0, dt_shrink=0.5, dt_grow=1.1,
+             grow_after=5)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def threads(orc):
+    import os
+    orc.set_threads(len(os.sched_getaffinity(0)))
+
+
+@pytest.mark.parametrize("name", ["spinodal2048", "nucleation2048"])
+def test_2048_first_steps_match_oracle(orc, name):
+    cfg = synth.CONFIGS[name]
+    h0 = cfg.film()
+    g = Grid(cfg.n, cfg.n, cfg.ds)
+    g.set_model(10.0, 0.1, 3, 2)
+    g.set_scheme(**ADAPT)
+    h = torch.from_numpy(h0).to(DEV)
+    g.bind(h)
+    nsteps = 4
+    _, log = g.advance(nsteps, cfg.dt, log=True)
+    M = orc.Model()
+    S = orc.Scheme(theta=1.0, **ADAPT)
+    u, dt, succ = h0, cfg.dt, 0
+    for s in range(nsteps):
+        u, res = orc.step(M, S, u, cfg.ds, dt, succ)
+        assert res.status == orc.OK
+        assert log[s]["dt_used"] == res.dt_used and log[s]["rejections"] == res.rejections
+        assert log[s]["newton_iters"] == res.newton_iters
+        dt, succ = res.dt_next, res.successes
+    got = h.cpu().numpy()
+    assert np.max(np.abs(got - u) / u) <= 1e-10
+
+
+def test_8192_newton_iteration_matches_oracle(orc):
+    cfg = synth.CONFIGS["large8192"]
+    h0 = cfg.film()
+    g = Grid(cfg.n, cfg.n, cfg.ds)
+    g.set_model(10.0, 0.1, 3, 2)
+    g.set_scheme(theta=1.0, tol=1e-10)
+    un = torch.from_numpy(h0).to(DEV)
+    out = torch.empty_like(un)
+    e, r, flags = g.newton_iteration(un, un, out, cfg.dt)
+    ref, e_ref, r_ref = orc.adi_iteration(orc.Model(), h0, h0, cfg.ds, cfg.dt, 1.0)
+    got = out.cpu().numpy()
+    v = ref - h0
+    assert flags == 0
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(v))
+    assert e == pytest.approx(e_ref, rel=1e-9)
+    assert r == pytest.approx(r_ref, rel=1e-9)
+
+
+def test_2048_long_run_mass_and_positivity():
+    cfg = synth.CONFIGS["spinodal2048"]
+    h0 = cfg.film()
+    g = Grid(cfg.n, cfg.n, cfg.ds)
+    g.set_model(10.0, 0.1, 3, 2)
+    g.set_scheme(**ADAPT)
+    g.set_diagnostics(True)
+    h = torch.from_numpy(h0).to(DEV)
+    g.bind(h)
+    m0, _ = g.mass()
+    dt = cfg.dt
+    for _ in range(4):
+        dt, log = g.advance(50, dt, log=True)
+        for x in log:
+            assert abs(x["mass"] - m0) <= 1e-12 * m0
+            assert x["hmin"] > 0.0
+    assert torch.isfinite(h).all()
