@@ -198,7 +198,9 @@ __global__ void __launch_bounds__(BLOCK) k_sb_pass(SBParams P)
     if (!SOLVE) {
         if (wave == 0 && owned) {
             Rel seg;
-            chain_symbolic(sB, lane, nsub, seg);
+            Rel first;
+            load_rel(sB, 0, lane, first);
+            chain_symbolic(first, sB + NREL * 64, lane, nsub, seg);
             double *o = P.rel + (size_t)q * NREL * P.nl + line;
 #pragma unroll
             for (int i = 0; i < 2; ++i)

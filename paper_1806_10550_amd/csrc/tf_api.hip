@@ -111,12 +111,10 @@ tf::PassParams base_params(const tf_grid *g, double dt)
     tf::PassParams P{};
     P.nx = g->nx;
     P.ny = g->ny;
-    P.ids = 1.0 / g->ds;
     P.ids2 = 1.0 / (g->ds * g->ds);
-    const double c = g->S.theta * dt;
-    P.k1 = c / g->ds;
-    P.k3 = c / (g->ds * g->ds * g->ds * g->ds);
-    P.cD = c;
+    P.ka = 0.5 * g->S.theta * dt * P.ids2;
+    P.K0 = 3.0 * P.ka * P.ids2;
+    P.K1 = P.ka * g->M.Dn;
     P.M = g->M;
     return P;
 }

@@ -143,8 +143,10 @@ __device__ __forceinline__ void load_rel(const double *sB, int q, int lane, Rel 
 // + N_0..N_{Q-1} T_Q.
 
 // Symbolic version: quantities are affine forms over (1, l1, l2, r1, r2), the tile's
-// outer boundary values. Returns the tile's relation record (T_0, B_{Q-1}).
-__device__ __forceinline__ void chain_symbolic(const double *sB, int lane, int Q, Rel &out)
+// outer boundary values. The record of sub-segment 0 comes in registers, those of
+// sub-segments 1..Q-1 from the LDS exchange area `rest`. Returns the tile's relation
+// record (T_0, B_{Q-1}).
+__device__ __forceinline__ void chain_symbolic(const Rel &first, const double *rest, int lane, int Q, Rel &out)
 {
     double bt[2][5], acc[2][5];
     M2 Mm = {0, 0, 0, 0}, P = {1, 0, 0, 1};
@@ -156,7 +158,8 @@ __device__ __forceinline__ void chain_symbolic(const double *sB, int lane, int Q
     for (int q = 0; q < NSUB; ++q) {
         if (q >= Q) break;
         Rel S;
-        load_rel(sB, q, lane, S);
+        if (q == 0) S = first;
+        else load_rel(rest, q - 1, lane, S);
         const M2 Tl = {S.T[0][1], S.T[0][2], S.T[1][1], S.T[1][2]};
         const M2 Tr = {S.T[0][3], S.T[0][4], S.T[1][3], S.T[1][4]};
         const M2 Bl = {S.B[0][1], S.B[0][2], S.B[1][1], S.B[1][2]};

@@ -53,9 +53,9 @@ struct Model {
 // Parameters of one sweep pass (K1 relations / K3 solve) over a grid or a packed film.
 struct PassParams {
     int nx, ny;
-    double ids, ids2;   // 1/ds, 1/ds^2
-    double k1, k3;      // c/ds, c/ds^4 with c = theta dt (band scale)
-    double cD;          // theta dt (scale of D(u_k) in the residual)
+    double ids2;        // 1/ds^2
+    double ka;          // c / (2 ds^2) with c = theta dt
+    double K0, K1;      // 3 ka / ds^2 (scale of h^2 in g0) and ka Dn (of r^2 in g1, n=3, m=2)
     Model M;
     const double *u;    // u_k
     const double *in2;  // y sweep: b^n (= u^n for backward Euler); x sweep: w

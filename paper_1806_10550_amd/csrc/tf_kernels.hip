@@ -23,11 +23,20 @@ namespace tf {
 #ifndef K3_WAVES_PER_EU
 #define K3_WAVES_PER_EU 2
 #endif
+#ifndef K1Y_WAVES_PER_EU
+#define K1Y_WAVES_PER_EU 4
+#endif
+#ifndef K1X_WAVES_PER_EU
+#define K1X_WAVES_PER_EU 2
+#endif
 #ifndef K1_UNROLL
 #define K1_UNROLL 1
 #endif
 #ifndef K1Y_FAST_UNROLL
-#define K1Y_FAST_UNROLL 8
+#define K1Y_FAST_UNROLL 2
+#endif
+#ifndef K1X_FAST_UNROLL
+#define K1X_FAST_UNROLL 16
 #endif
 
 // ------------------------------------------------------------------------------------
@@ -36,22 +45,85 @@ namespace tf {
 // y-sweep tiles own LT0 = 62 columns: lanes 0 and 63 carry the neighbouring columns so
 // that the x faces of the residual come from lane shuffles.
 // ------------------------------------------------------------------------------------
+// Per-cell quantities of the sweeps, scaled so that each face record takes few
+// operations (ka = c / (2 ds^2), c = theta dt):
+//   lap = u_E + u_W + u_N + u_S - 4u      (ds^2 times the 5-point Laplacian)
+//   f0  = h^3 / ds^2,   f1 = kappa h^3 f'(h)
+//   g0  = ka f0'(h) / ds^2,   g1 = ka f1'(h)
+struct CellS {
+    double u, lap, f0, f1, g0, g1;
+};
+
+template <int DIR, bool P32>
+__device__ __forceinline__ CellS cell_s(const double *sU, const PassParams &p, int l, int q)
+{
+    CellS c;
+    c.u = uat<DIR>(sU, l, q);
+    double xp, xm, yp, ym;
+    if (DIR == 0) {
+        xp = uat<DIR>(sU, l + 1, q); xm = uat<DIR>(sU, l - 1, q);
+        yp = uat<DIR>(sU, l, q + 1); ym = uat<DIR>(sU, l, q - 1);
+    } else {
+        xp = uat<DIR>(sU, l, q + 1); xm = uat<DIR>(sU, l, q - 1);
+        yp = uat<DIR>(sU, l + 1, q); ym = uat<DIR>(sU, l - 1, q);
+    }
+    c.lap = __builtin_fma(-4.0, c.u, (xp + xm) + (yp + ym));
+    const double r = rcp(c.u);
+    const double u2 = c.u * c.u;
+    c.f0 = (u2 * c.u) * p.ids2;
+    c.g0 = p.K0 * u2;
+    if (P32) {
+        c.f1 = __builtin_fma(-p.M.Cn, r, p.M.Cm);
+        c.g1 = p.K1 * (r * r);
+    } else {
+        const Model &M = p.M;
+        c.f1 = M.Cm * ipow(r, c.u, M.m - 2) - M.Cn * ipow(r, c.u, M.n - 2);
+        c.g1 = p.ka * (M.Dn * ipow(r, c.u, M.n - 1) - M.Dm * ipow(r, c.u, M.m - 1));
+    }
+    return c;
+}
+
+// Face record between the cells L and R of a line (raw differences Lam = lap_R - lap_L,
+// Gam = u_R - u_L; A and B are the face means of f0 and f1):
+//   kA = c A / ds^4,
+//   P  = c/ds d(flux)/du_L without the fourth-difference part = ka (f0'_L Lam/ds^2 + f1'_L Gam - 2B),
+//   Q  = the same for u_R with +2B,
+//   F  = 2 ds times the face flux A (lap_R - lap_L)/ds^3 + B Gam/ds  (y sweep only).
+// Boundary faces carry no flux: every entry is zero there.
+struct FaceS {
+    double kA, P, Q, F;
+};
+
+template <bool FLUX>
+__device__ __forceinline__ FaceS face_s(const CellS &L, const CellS &R, bool interior, double ka)
+{
+    const double S0 = L.f0 + R.f0, S1 = L.f1 + R.f1;
+    const double Lam = R.lap - L.lap, Gam = R.u - L.u;
+    const double kS1 = ka * S1;
+    FaceS f;
+    f.kA = interior ? ka * S0 : 0.0;
+    f.P = interior ? __builtin_fma(L.g0, Lam, __builtin_fma(L.g1, Gam, -kS1)) : 0.0;
+    f.Q = interior ? __builtin_fma(R.g0, Lam, __builtin_fma(R.g1, Gam, kS1)) : 0.0;
+    f.F = (FLUX && interior) ? __builtin_fma(S0, Lam, S1 * Gam) : 0.0;
+    return f;
+}
+
 // Elimination sweep of one wave over its sub-segment [ps, ps+len) for all 64 lanes:
-// assembles, per position, the cell coefficients, the residual (y sweep) and the five
+// assembles, per position, the cell quantities, the residual (y sweep) and the five
 // bands of I + c J, and runs the LU step with the sub-segment's outer unknowns kept
 // symbolic. FAST: interior tile with 16 positions per wave, no domain boundary inside
 // (no folded ghost columns, no zero-flux faces, no per-lane boundary selects).
 template <int DIR, bool SOLVE, bool P32, bool FAST>
-__device__ __forceinline__ void sweep(const double *sU, const double *sB, const PassParams &p, int lane, int ps,
-                                      int len, int pbase, int Np, int gl, int Nl, bool owned, double *fa,
+__device__ __forceinline__ void sweep(const double *sU, const double *sB, const double *bcol, const PassParams &p,
+                                      int lane, int ps, int len, int pbase, int Np, int gl, int Nl, bool owned, double *fa,
                                       double *fb, double *fz, double *fph, double *fps, Rel &mine,
                                       double &rmax, unsigned &flags)
 {
-    const double ids = p.ids, ids2 = p.ids2, k1 = p.k1, k3 = p.k3;
+    const double ka = p.ka;
     {
-        const Cell cm = cell_at<DIR, P32>(sU, p.M, ids2, lane, ps - 1);
-        Cell c0 = cell_at<DIR, P32>(sU, p.M, ids2, lane, ps);
-        FaceQ fm = face_q<DIR == 0>(cm, c0, FAST || pbase + ps > 0, ids, k1, k3);
+        const CellS cm = cell_s<DIR, P32>(sU, p, lane, ps - 1);
+        CellS c0 = cell_s<DIR, P32>(sU, p, lane, ps);
+        FaceS fm = face_s<DIR == 0>(cm, c0, FAST || pbase + ps > 0, ka);
         double al1 = 0.0, be1 = 0.0, al2 = 0.0, be2 = 0.0;
         // rows s-2 and s-1 stand for the outer unknowns l1 and l2
         double z1 = 0.0, ph1 = 0.0, ps1 = 1.0, z2 = 0.0, ph2 = 1.0, ps2 = 0.0;
@@ -59,26 +131,27 @@ __device__ __forceinline__ void sweep(const double *sU, const double *sB, const 
         double sgz = 0.0, sgph = 0.0, sgps = 0.0, shz = 0.0, shph = 0.0, shps = 0.0;
         // the solve pass keeps per-position factors in registers (full unroll); the
         // relations pass needs none and, off the interior path, is only partly unrolled
-        constexpr int UNR = SOLVE ? SUB : (FAST ? (DIR == 0 ? K1Y_FAST_UNROLL : SUB) : K1_UNROLL);
+        constexpr int UNR = SOLVE ? SUB : (FAST ? (DIR == 0 ? K1Y_FAST_UNROLL : K1X_FAST_UNROLL) : K1_UNROLL);
 #pragma unroll UNR
         for (int k = 0; k < SUB; ++k) {
             if (FAST || k < len) {
                 const int lp = ps + k;
                 const int gp = pbase + lp;          // wave-uniform
-                const Cell cp = cell_at<DIR, P32>(sU, p.M, ids2, lane, lp + 1);
-                const FaceQ fp = face_q<DIR == 0>(c0, cp, FAST || gp < Np - 1, ids, k1, k3);
+                const CellS cp = cell_s<DIR, P32>(sU, p, lane, lp + 1);
+                const FaceS fp = face_s<DIR == 0>(c0, cp, FAST || gp < Np - 1, ka);
                 double rhs;
                 if (DIR == 0) {
                     // -G(u_k) = -(u_k - b^n + theta dt D(u_k)); the x faces of this cell
                     // use the neighbouring lanes' cell values
                     const double eu = __shfl_down(c0.u, 1), el = __shfl_down(c0.lap, 1);
                     const double e0 = __shfl_down(c0.f0, 1), e1 = __shfl_down(c0.f1, 1);
-                    const double Fe0 = 0.5 * (c0.f0 + e0) * ((el - c0.lap) * ids) + 0.5 * (c0.f1 + e1) * ((eu - c0.u) * ids);
+                    const double Fe0 = __builtin_fma(c0.f0 + e0, el - c0.lap, (c0.f1 + e1) * (eu - c0.u));
                     const double Fe = (FAST || gl < Nl - 1) ? Fe0 : 0.0;
                     const double Fwr = __shfl_up(Fe, 1);
                     const double Fw = (FAST || gl > 0) ? Fwr : 0.0;
-                    const double D = (Fe - Fw + fp.F - fm.F) * ids;
-                    const double G = c0.u - sB[lp * WPITCH + lane] + p.cD * D;
+                    const double D = (Fe - Fw) + (fp.F - fm.F);
+                    const double bn = SOLVE ? sB[lp * WPITCH + lane] : bcol[(size_t)gp * p.nx];
+                    const double G = __builtin_fma(ka, D, c0.u - bn);
                     rhs = -G;
                     if (!SOLVE && owned) {
                         rmax = fmax(rmax, fabs(G));
@@ -89,9 +162,9 @@ __device__ __forceinline__ void sweep(const double *sU, const double *sB, const 
                 }
                 // bands of I + c J along the line from the two face records
                 double a = fm.kA;
-                double b = -fp.kA - 3.0 * fm.kA - fm.P;
-                double c = 1.0 + 3.0 * fp.kA + fp.P + 3.0 * fm.kA - fm.Q;
-                double d = -3.0 * fp.kA + fp.Q - fm.kA;
+                double b = __builtin_fma(-3.0, fm.kA, -fp.kA) - fm.P;
+                double c = __builtin_fma(3.0, fp.kA + fm.kA, 1.0) + (fp.P - fm.Q);
+                double d = __builtin_fma(-3.0, fp.kA, fp.Q) - fm.kA;
                 double e = fp.kA;
                 if (!FAST) {
                     // fold ghost columns back (even reflection of the perturbation)
@@ -137,14 +210,88 @@ __device__ __forceinline__ void sweep(const double *sU, const double *sB, const 
     }
 }
 
+// Stage the haloed u tile and (STAGE_B) the tile of the second input (b^n or w) in LDS.
+// Tile row ly holds grid row y0 - HALO + ly (u) or y0 + ly (second input); tile column lx
+// holds grid column bxo - HALO + lx (u) or bxo + lx. Every load covers (part of) one grid row, so its row
+// address is wave-uniform and only the column offset is per lane; all global loads are
+// issued before the first LDS store. Only the u cells the sweeps read are staged:
+// rows 0..67 x columns 1..66 (y sweep) and rows 1..66 x columns 0..67 (x sweep).
+template <int DIR, bool STAGE_B>
+__device__ __forceinline__ void stage_tile(const PassParams &p, double *sU, double *sB, int bxo, int y0, int wave,
+                                           int lane)
+{
+    constexpr int LX0 = DIR == 0 ? 1 : 2;         // tile column of lane 0 in a row load
+    constexpr int RU0 = DIR == 0 ? 0 : 1;         // first u tile row read by the sweeps
+    constexpr int NRU = DIR == 0 ? TW : TW - 2;   // u tile rows read by the sweeps
+    constexpr int KU = (NRU + NSUB - 1) / NSUB;   // row loads per wave
+    constexpr int KB = TILE / NSUB;
+    // the columns outside the lanes' span: 2 per row (y sweep) or 4 per row (x sweep)
+    constexpr int XPR = DIR == 0 ? 2 : 4;
+    constexpr int NX = NRU * XPR;
+    constexpr int KX = (NX + BLOCK - 1) / BLOCK;  // packed extra loads per wave
+    const int nx = p.nx, ny = p.ny;
+    const unsigned cu = (unsigned)crefl(bxo - HALO + LX0 + lane, nx);
+    const unsigned cb = (unsigned)crefl(bxo + lane, nx);
+    double vu[KU], vb[KB], vx[KX];
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+        const int ly = RU0 + wave + NSUB * k;
+        if (ly < RU0 + NRU) {
+            const int gy = crefl(y0 - HALO + ly, ny);
+            vu[k] = (p.u + (size_t)gy * nx)[cu];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        if (STAGE_B) {
+            const int gy = min(y0 + wave + NSUB * k, ny - 1);
+            vb[k] = (p.in2 + (size_t)gy * nx)[cb];
+        }
+    }
+    int xoff[KX];
+#pragma unroll
+    for (int k = 0; k < KX; ++k) {
+        const int idx = (wave + NSUB * k) * 64 + lane;
+        xoff[k] = -1;
+        if (idx < NX) {
+            const int ly = RU0 + idx / XPR, q = idx % XPR;
+            const int lx = DIR == 0 ? LX0 + 64 + q : (q < 2 ? q : 64 + q);
+            const int gy = crefl(y0 - HALO + ly, ny), gx = crefl(bxo - HALO + lx, nx);
+            vx[k] = p.u[(size_t)gy * nx + gx];
+            xoff[k] = ly * UPITCH + lx;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+        const int ly = RU0 + wave + NSUB * k;
+        if (ly < RU0 + NRU) sU[ly * UPITCH + LX0 + lane] = vu[k];
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        if (STAGE_B) sB[(wave + NSUB * k) * WPITCH + lane] = vb[k];
+#pragma unroll
+    for (int k = 0; k < KX; ++k)
+        if (xoff[k] >= 0) sU[xoff[k]] = vx[k];
+}
+
 template <int DIR, bool SOLVE, bool P32>
 __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
 {
-    __shared__ double sU[TW * UPITCH];
-    __shared__ double sB[NSUB * NREL * 64];
+    // LDS: the u tile, then the tile of the second input (b^n, w) which the solve passes
+    // later reuse for the relation exchange and (x solve) the output tile. The relations
+    // passes exchange in the u tile once the sweeps are done. The y relations pass reads
+    // b^n straight from global memory (lanes cover consecutive x), which keeps its LDS
+    // footprint at one tile, so that four workgroups fit on a CU.
+    constexpr int NU = TW * UPITCH, NX = NSUB * NREL * 64, NW = TILE * WPITCH;
+    constexpr bool STAGE_B = DIR == 1 || SOLVE;
+    constexpr int NLDS = SOLVE ? NU + NX : (STAGE_B ? NU + NW : NU);
+    static_assert(NX >= NW && NU >= (NSUB - 1) * NREL * 64, "LDS regions too small");
+    __shared__ double lds[NLDS];
     __shared__ double sRed[NSUB];
     __shared__ unsigned sFlag[NSUB];
-    static_assert(NSUB * NREL * 64 >= TILE * WPITCH, "second LDS region too small");
+    double *const sU = lds;
+    double *const sB = lds + NU;                 // second input, then exchange / output
+    double *const xch = SOLVE ? sB : lds;        // relation exchange
 
     const int nx = p.nx, ny = p.ny;
     int x0, x1, y0, y1;
@@ -156,39 +303,10 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
         y0 = ty * TILE; y1 = min(y0 + TILE, ny);
     }
     const int bxo = DIR == 0 ? x0 - 1 : x0;  // grid x of lane/position 0 of the tile
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-
-    {
-        // issue every global load of the tile before the first LDS store
-        constexpr int NU = (TW * TW + BLOCK - 1) / BLOCK, NB = TILE * TILE / BLOCK;
-        double vu[NU], vb[NB];
-#pragma unroll
-        for (int r = 0; r < NU; ++r) {
-            const int idx = tid + r * BLOCK;
-            const int ly = min(idx / TW, TW - 1), lx = idx - (idx / TW) * TW;
-            const int gx = crefl(bxo - HALO + lx, nx), gy = crefl(y0 - HALO + ly, ny);
-            vu[r] = idx < TW * TW ? p.u[(size_t)gy * nx + gx] : 0.0;
-        }
-#pragma unroll
-        for (int r = 0; r < NB; ++r) {
-            const int idx = tid + r * BLOCK;
-            const int ly = idx >> 6, lx = idx & 63;
-            const int gx = crefl(bxo + lx, nx), gy = min(y0 + ly, ny - 1);
-            vb[r] = p.in2[(size_t)gy * nx + gx];
-        }
-#pragma unroll
-        for (int r = 0; r < NU; ++r) {
-            const int idx = tid + r * BLOCK;
-            const int ly = idx / TW, lx = idx - ly * TW;
-            if (idx < TW * TW) sU[ly * UPITCH + lx] = vu[r];
-        }
-#pragma unroll
-        for (int r = 0; r < NB; ++r) {
-            const int idx = tid + r * BLOCK;
-            sB[(idx >> 6) * WPITCH + (idx & 63)] = vb[r];
-        }
-    }
+    stage_tile<DIR, STAGE_B>(p, sU, sB, bxo, y0, wave, lane);
     __syncthreads();
 
     const int lane0 = DIR == 0 ? 1 : 0;                 // first lane that owns a line
@@ -211,13 +329,15 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
     // interior tiles take the specialised path (wave-uniform branch)
     const bool fast = npos == TILE && pbase >= 2 && pbase + TILE <= Np - 2
                       && (DIR == 1 || (x0 > 0 && x0 + LT0 < nx && nlt == LT0));
+    // per-lane column of b^n for the y relations pass (read from global memory)
+    const double *bcol = p.in2 + crefl(bxo + lane, nx);
     if (len > 0) {
         if (fast)
-            sweep<DIR, SOLVE, P32, true>(sU, sB, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph, fps,
-                                         mine, rmax, flags);
+            sweep<DIR, SOLVE, P32, true>(sU, sB, bcol, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph,
+                                         fps, mine, rmax, flags);
         else
-            sweep<DIR, SOLVE, P32, false>(sU, sB, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph, fps,
-                                          mine, rmax, flags);
+            sweep<DIR, SOLVE, P32, false>(sU, sB, bcol, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph,
+                                          fps, mine, rmax, flags);
     }
 
     if (!SOLVE && DIR == 0 && p.res != nullptr) {
@@ -225,9 +345,11 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
         const unsigned wf = wave_or(flags);
         if (lane == 0) { sRed[wave] = wm; sFlag[wave] = wf; }
     }
-    __syncthreads(); // all sweeps done: sB may be reused for the relation exchange
-    if (len > 0) {
-        double *dst = sB + (size_t)wave * NREL * 64 + lane;
+    __syncthreads(); // all sweeps done: the exchange area may be overwritten
+    // the relations pass hands the records of waves 1.. to wave 0, which keeps its own
+    const int xslot = SOLVE ? wave : wave - 1;
+    if (len > 0 && xslot >= 0) {
+        double *dst = xch + (size_t)xslot * NREL * 64 + lane;
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -248,14 +370,14 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
         }
         if (wave == 0 && owned) {
             Rel seg;
-            chain_symbolic(sB, lane, nsub, seg);
-            double *o = p.rel + (size_t)qseg * NREL * Nl + gl;
+            chain_symbolic(mine, xch, lane, nsub, seg);
+            double *o = p.rel + (size_t)qseg * NREL * Nl;
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 5; ++j) {
-                    o[(size_t)(i * 5 + j) * Nl] = seg.T[i][j];
-                    o[(size_t)(10 + i * 5 + j) * Nl] = seg.B[i][j];
+                    (o + (size_t)(i * 5 + j) * Nl)[(unsigned)gl] = seg.T[i][j];
+                    (o + (size_t)(10 + i * 5 + j) * Nl)[(unsigned)gl] = seg.B[i][j];
                 }
         }
         return;
@@ -264,9 +386,11 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
     // ---- SOLVE: boundary values of this wave's sub-segment, then back-substitution
     double wl1 = 0.0, wl2 = 0.0, xr1 = 0.0, xr2 = 0.0;
     if (len > 0) {
-        const double *ex = p.ext + (size_t)qseg * NEXT * Nl + min(max(gl, 0), Nl - 1);
-        const double l1 = ex[0], l2 = ex[(size_t)Nl], r1 = ex[(size_t)2 * Nl], r2 = ex[(size_t)3 * Nl];
-        chain_numeric(sB, lane, nsub, wave, l1, l2, r1, r2, wl1, wl2, xr1, xr2);
+        const double *ex = p.ext + (size_t)qseg * NEXT * Nl;
+        const unsigned gc = (unsigned)min(max(gl, 0), Nl - 1);
+        const double l1 = ex[gc], l2 = (ex + (size_t)Nl)[gc];
+        const double r1 = (ex + (size_t)2 * Nl)[gc], r2 = (ex + (size_t)3 * Nl)[gc];
+        chain_numeric(xch, lane, nsub, wave, l1, l2, r1, r2, wl1, wl2, xr1, xr2);
     }
 
     if (DIR == 0) {
@@ -276,7 +400,7 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
             for (int k = SUB - 1; k >= 0; --k) {
                 if (k < len) {
                     const double x = fz[k] + fph[k] * wl1 + fps[k] * wl2 - fa[k] * xr1 - fb[k] * xr2;
-                    if (owned) p.out[(size_t)(pbase + ps + k) * nx + gl] = x;
+                    if (owned) (p.out + (size_t)(pbase + ps + k) * nx)[(unsigned)gl] = x;
                     xr2 = xr1;
                     xr1 = x;
                 }
@@ -307,9 +431,10 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
         const unsigned wf = wave_or(flags);
         if (lane == 0) { sRed[wave] = wm; sFlag[wave] = wf; }
         __syncthreads();
-        for (int idx = tid; idx < TILE * TILE; idx += BLOCK) {
-            const int ly = idx >> 6, lx = idx & 63;
-            if (ly < nlt && lx < npos) p.out[(size_t)(y0 + ly) * nx + x0 + lx] = sB[ly * WPITCH + lx];
+#pragma unroll
+        for (int r = 0; r < TILE / NSUB; ++r) {
+            const int ly = wave + NSUB * r;
+            if (ly < nlt && lane < npos) (p.out + (size_t)(y0 + ly) * nx + x0)[(unsigned)lane] = sB[ly * WPITCH + lane];
         }
         if (tid == 0 && p.res != nullptr) {
             double m = 0.0;
@@ -323,7 +448,11 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
 
 #define TF_PASS_ATTR                                                                         \
     __launch_bounds__(BLOCK)                                                                 \
-    __attribute__((amdgpu_waves_per_eu(SOLVE ? K3_WAVES_PER_EU : 2, SOLVE ? K3_WAVES_PER_EU : 2)))
+    __attribute__((amdgpu_waves_per_eu(TF_PASS_WPE, TF_PASS_WPE)))
+// waves per SIMD the pass is compiled for: the relations passes of the n = 3, m = 2
+// model fit in 128 VGPRs (their LDS footprint admits 4 workgroups per CU); the solve
+// passes hold their factors in registers
+#define TF_PASS_WPE (SOLVE ? K3_WAVES_PER_EU : (!P32 ? 2 : (DIR == 0 ? K1Y_WAVES_PER_EU : K1X_WAVES_PER_EU)))
 
 template <int DIR, bool SOLVE, bool P32>
 __global__ void TF_PASS_ATTR k_pass(PassParams p)
@@ -348,12 +477,10 @@ __global__ void TF_PASS_ATTR k_pass_ens(EnsParams e)
     PassParams p{};
     p.nx = d.nx;
     p.ny = d.ny;
-    p.ids = 1.0 / d.ds;
     p.ids2 = 1.0 / (d.ds * d.ds);
-    const double c = e.theta * s->dt;
-    p.k1 = c / d.ds;
-    p.k3 = c / (d.ds * d.ds * d.ds * d.ds);
-    p.cD = c;
+    p.ka = 0.5 * e.theta * s->dt * p.ids2;
+    p.K0 = 3.0 * p.ka * p.ids2;
+    p.K1 = p.ka * d.M.Dn;
     p.M = d.M;
     p.u = B[s->it] + d.off;
     p.in2 = DIR == 0 ? B[s->cur] + d.off : e.w + d.off;
@@ -365,9 +492,16 @@ __global__ void TF_PASS_ATTR k_pass_ens(EnsParams e)
 }
 
 // ------------------------------------------------------------------------------------
-// Interface chain: per line, block elimination over the P segments (outer boundary
-// values are zero at the two ends of the line), then back-substitution giving every
-// segment its two left and two right neighbouring values.
+// Interface chain. Per line, the segment relations
+//   T_q = t_q + Tl_q B_{q-1} + Tr_q T_{q+1},   B_q = b_q + Bl_q B_{q-1} + Br_q T_{q+1}
+// (T_q, B_q: top and bottom pairs of segment q; B_{-1} = T_P = 0 at the line ends)
+// form a block-tridiagonal system in 2x2 blocks. It is eliminated from both ends at
+// once: one wave sweeps segments 0..m-1 forward,
+//   B_q = bt_q + M_q T_{q+1},  T_q = tau_q + N_q T_{q+1},
+// the other sweeps segments P-1..m backward,
+//   T_q = tt_q + R_q B_{q-1},  B_q = bb_q + S_q B_{q-1},
+// the two meet at the pair (B_{m-1}, T_m), and each substitutes back over its half,
+// giving every segment its two left (B_{q-1}) and two right (T_{q+1}) neighbours.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ void load_rec(const double *r, size_t NL, double (&T)[2][5], double (&B)[2][5])
 {
@@ -380,106 +514,201 @@ __device__ __forceinline__ void load_rec(const double *r, size_t NL, double (&T)
         }
 }
 
-__device__ __forceinline__ void chain_body(const ChainParams &c, int line)
+__device__ __forceinline__ void copy_rec(double (&dT)[2][5], double (&dB)[2][5], const double (&T)[2][5],
+                                         const double (&B)[2][5])
+{
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) { dT[i][j] = T[i][j]; dB[i][j] = B[i][j]; }
+}
+
+__device__ __forceinline__ void store6(double *w, size_t NL, double a0, double a1, const M2 &X)
+{
+    w[0] = a0; w[NL] = a1; w[2 * NL] = X.a; w[3 * NL] = X.b; w[4 * NL] = X.c; w[5 * NL] = X.d;
+}
+
+__device__ __forceinline__ void load6(const double *w, size_t NL, double &a0, double &a1, M2 &X)
+{
+    a0 = w[0]; a1 = w[NL]; X.a = w[2 * NL]; X.b = w[3 * NL]; X.c = w[4 * NL]; X.d = w[5 * NL];
+}
+
+// Meeting record of one line: the forward wave leaves (bt_{m-1}, M_{m-1}), the backward
+// wave (tt_m, R_m).
+struct ChainMeet {
+    double v[12][64];
+};
+
+__device__ __forceinline__ void chain_line(const ChainParams &c, int line, int wave, int lane, ChainMeet &mt)
 {
     const size_t NL = (size_t)c.nlines;
-    const size_t RS = (size_t)NREL * NL; // stride between segment records
-    double tau0 = 0.0, tau1 = 0.0, bt0 = 0.0, bt1 = 0.0;
-    M2 N = {0, 0, 0, 0}, Mm = {0, 0, 0, 0};
+    const size_t RS = (size_t)NREL * NL, CS = (size_t)NCHAIN * NL, ES = (size_t)NEXT * NL;
+    const int P = c.P, m = P / 2;
+    const bool live = line < c.nlines;
+    const double *rb = c.rel + line;
+    double *cb = c.chain + line;
+    double *eb = c.ext + line;
     // records are loaded two segments ahead of their use to hide memory latency
     double T[2][5], B[2][5], Tn[2][5], Bn[2][5], Tnn[2][5], Bnn[2][5];
-    const double *base = c.rel + line;
-    load_rec(base, NL, T, B);
-    if (c.P > 1) load_rec(base + RS, NL, Tn, Bn);
-    for (int q = 0; q < c.P; ++q) {
-        if (q + 2 < c.P) load_rec(base + (size_t)(q + 2) * RS, NL, Tnn, Bnn);
-        const M2 Tl = {T[0][1], T[0][2], T[1][1], T[1][2]};
-        const M2 Tr = {T[0][3], T[0][4], T[1][3], T[1][4]};
-        const M2 Bl = {B[0][1], B[0][2], B[1][1], B[1][2]};
-        const M2 Br = {B[0][3], B[0][4], B[1][3], B[1][4]};
-        if (q == 0) {
-            tau0 = T[0][0]; tau1 = T[1][0]; N = Tr;
-            bt0 = B[0][0]; bt1 = B[1][0]; Mm = Br;
-        } else {
-            const M2 K = inv_i_minus(mul(Tl, Mm));
-            const double s0 = T[0][0] + Tl.a * bt0 + Tl.b * bt1;
-            const double s1 = T[1][0] + Tl.c * bt0 + Tl.d * bt1;
-            const double nt0 = K.a * s0 + K.b * s1, nt1 = K.c * s0 + K.d * s1;
-            const M2 nN = mul(K, Tr);
-            const double v0 = bt0 + Mm.a * nt0 + Mm.b * nt1;
-            const double v1 = bt1 + Mm.c * nt0 + Mm.d * nt1;
-            const M2 BM = mul(mul(Bl, Mm), nN);
-            tau0 = nt0; tau1 = nt1; N = nN;
-            bt0 = B[0][0] + Bl.a * v0 + Bl.b * v1;
-            bt1 = B[1][0] + Bl.c * v0 + Bl.d * v1;
-            Mm = {BM.a + Br.a, BM.b + Br.b, BM.c + Br.c, BM.d + Br.d};
-        }
-        double *w = c.chain + (size_t)q * NCHAIN * NL + line;
-        w[0] = tau0; w[NL] = tau1; w[2 * NL] = N.a; w[3 * NL] = N.b; w[4 * NL] = N.c; w[5 * NL] = N.d;
-        w[6 * NL] = bt0; w[7 * NL] = bt1; w[8 * NL] = Mm.a; w[9 * NL] = Mm.b; w[10 * NL] = Mm.c;
-        w[11 * NL] = Mm.d;
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                T[i][j] = Tn[i][j]; B[i][j] = Bn[i][j];
-                Tn[i][j] = Tnn[i][j]; Bn[i][j] = Bnn[i][j];
+    double x0 = 0.0, x1 = 0.0;   // wave 0: bt_{q}; wave 1: tt_{q}
+    M2 X = {0, 0, 0, 0};         // wave 0: M_{q};  wave 1: R_{q}
+    if (wave == 0) {
+        // forward over q = 0..m-1: chain record (tau_q, N_q, bt_q, M_q)
+        if (live && m > 0) {
+            load_rec(rb, NL, T, B);
+            if (m > 1) load_rec(rb + RS, NL, Tn, Bn);
+            for (int q = 0; q < m; ++q) {
+                if (q + 2 < m) load_rec(rb + (size_t)(q + 2) * RS, NL, Tnn, Bnn);
+                const M2 Tl = {T[0][1], T[0][2], T[1][1], T[1][2]}, Tr = {T[0][3], T[0][4], T[1][3], T[1][4]};
+                const M2 Bl = {B[0][1], B[0][2], B[1][1], B[1][2]}, Br = {B[0][3], B[0][4], B[1][3], B[1][4]};
+                double tau0, tau1;
+                M2 N;
+                if (q == 0) {
+                    tau0 = T[0][0]; tau1 = T[1][0]; N = Tr;
+                    x0 = B[0][0]; x1 = B[1][0]; X = Br;
+                } else {
+                    const M2 K = inv_i_minus(mul(Tl, X));
+                    const double s0 = T[0][0] + Tl.a * x0 + Tl.b * x1;
+                    const double s1 = T[1][0] + Tl.c * x0 + Tl.d * x1;
+                    tau0 = K.a * s0 + K.b * s1;
+                    tau1 = K.c * s0 + K.d * s1;
+                    N = mul(K, Tr);
+                    const double v0 = x0 + X.a * tau0 + X.b * tau1;
+                    const double v1 = x1 + X.c * tau0 + X.d * tau1;
+                    const M2 BM = mul(mul(Bl, X), N);
+                    x0 = B[0][0] + Bl.a * v0 + Bl.b * v1;
+                    x1 = B[1][0] + Bl.c * v0 + Bl.d * v1;
+                    X = {BM.a + Br.a, BM.b + Br.b, BM.c + Br.c, BM.d + Br.d};
+                }
+                double *w = cb + (size_t)q * CS;
+                store6(w, NL, tau0, tau1, N);
+                store6(w + 6 * NL, NL, x0, x1, X);
+                copy_rec(T, B, Tn, Bn);
+                copy_rec(Tn, Bn, Tnn, Bnn);
             }
-    }
-    // backward substitution; the chain records of segments q and q-1 are read ahead
-    double tn0 = 0.0, tn1 = 0.0;
-    const double *cb = c.chain + line;
-    const size_t CS = (size_t)NCHAIN * NL;
-    double cq[6], cp[6], cpp[6]; // (tau0, tau1, N) of q; (bt0, bt1, M) of q-1
-    auto ld_t = [&](int q, double *o) {
-        const double *w = cb + (size_t)q * CS;
-        for (int k = 0; k < 6; ++k) o[k] = w[(size_t)k * NL];
-    };
-    auto ld_b = [&](int q, double *o) {
-        const double *w = cb + (size_t)q * CS + 6 * NL;
-        for (int k = 0; k < 6; ++k) o[k] = w[(size_t)k * NL];
-    };
-    ld_t(c.P - 1, cq);
-    if (c.P > 1) ld_b(c.P - 2, cp);
-    for (int q = c.P - 1; q >= 0; --q) {
-        double nq[6] = {0, 0, 0, 0, 0, 0};
-        if (q > 0) ld_t(q - 1, nq);
-        if (q > 1) ld_b(q - 2, cpp);
-        const double t0 = cq[0] + cq[2] * tn0 + cq[3] * tn1;
-        const double t1 = cq[1] + cq[4] * tn0 + cq[5] * tn1;
-        double *e = c.ext + (size_t)q * NEXT * NL + line;
-        e[2 * NL] = tn0;
-        e[3 * NL] = tn1;
-        if (q > 0) {
-            e[0] = cp[0] + cp[2] * t0 + cp[3] * t1;
-            e[NL] = cp[1] + cp[4] * t0 + cp[5] * t1;
-        } else {
-            e[0] = 0.0;
-            e[NL] = 0.0;
         }
-        tn0 = t0;
-        tn1 = t1;
-        for (int k = 0; k < 6; ++k) { cq[k] = nq[k]; cp[k] = cpp[k]; }
+    } else {
+        // backward over q = P-1..m: chain record (tt_q, R_q, bb_q, S_q)
+        if (live) {
+            load_rec(rb + (size_t)(P - 1) * RS, NL, T, B);
+            if (P - 2 >= m) load_rec(rb + (size_t)(P - 2) * RS, NL, Tn, Bn);
+            for (int q = P - 1; q >= m; --q) {
+                if (q - 2 >= m) load_rec(rb + (size_t)(q - 2) * RS, NL, Tnn, Bnn);
+                const M2 Tl = {T[0][1], T[0][2], T[1][1], T[1][2]}, Tr = {T[0][3], T[0][4], T[1][3], T[1][4]};
+                const M2 Bl = {B[0][1], B[0][2], B[1][1], B[1][2]}, Br = {B[0][3], B[0][4], B[1][3], B[1][4]};
+                double bb0, bb1;
+                M2 S;
+                if (q == P - 1) {
+                    bb0 = B[0][0]; bb1 = B[1][0]; S = Bl;
+                    x0 = T[0][0]; x1 = T[1][0]; X = Tl;
+                } else {
+                    const M2 K = inv_i_minus(mul(Br, X));
+                    const double s0 = B[0][0] + Br.a * x0 + Br.b * x1;
+                    const double s1 = B[1][0] + Br.c * x0 + Br.d * x1;
+                    bb0 = K.a * s0 + K.b * s1;
+                    bb1 = K.c * s0 + K.d * s1;
+                    S = mul(K, Bl);
+                    const double v0 = x0 + X.a * bb0 + X.b * bb1;
+                    const double v1 = x1 + X.c * bb0 + X.d * bb1;
+                    const M2 TRS = mul(mul(Tr, X), S);
+                    x0 = T[0][0] + Tr.a * v0 + Tr.b * v1;
+                    x1 = T[1][0] + Tr.c * v0 + Tr.d * v1;
+                    X = {TRS.a + Tl.a, TRS.b + Tl.b, TRS.c + Tl.c, TRS.d + Tl.d};
+                }
+                double *w = cb + (size_t)q * CS;
+                store6(w, NL, x0, x1, X);
+                store6(w + 6 * NL, NL, bb0, bb1, S);
+                copy_rec(T, B, Tn, Bn);
+                copy_rec(Tn, Bn, Tnn, Bnn);
+            }
+        }
+    }
+    // meet: B_{m-1} = bt + M T_m and T_m = tt + R B_{m-1}
+    mt.v[wave * 6 + 0][lane] = x0; mt.v[wave * 6 + 1][lane] = x1;
+    mt.v[wave * 6 + 2][lane] = X.a; mt.v[wave * 6 + 3][lane] = X.b;
+    mt.v[wave * 6 + 4][lane] = X.c; mt.v[wave * 6 + 5][lane] = X.d;
+    __syncthreads();
+    if (!live) return;
+    const double bt0 = mt.v[0][lane], bt1 = mt.v[1][lane];
+    const M2 Mm = {mt.v[2][lane], mt.v[3][lane], mt.v[4][lane], mt.v[5][lane]};
+    const double tt0 = mt.v[6][lane], tt1 = mt.v[7][lane];
+    const M2 Rm = {mt.v[8][lane], mt.v[9][lane], mt.v[10][lane], mt.v[11][lane]};
+    double Bm0 = 0.0, Bm1 = 0.0; // B_{m-1}
+    if (m > 0) {
+        const M2 K = inv_i_minus(mul(Mm, Rm));
+        const double s0 = bt0 + Mm.a * tt0 + Mm.b * tt1, s1 = bt1 + Mm.c * tt0 + Mm.d * tt1;
+        Bm0 = K.a * s0 + K.b * s1;
+        Bm1 = K.c * s0 + K.d * s1;
+    }
+    const double Tm0 = tt0 + Rm.a * Bm0 + Rm.b * Bm1, Tm1 = tt1 + Rm.c * Bm0 + Rm.d * Bm1; // T_m
+    if (wave == 0) {
+        // q = m-1..0: T_q = tau_q + N_q T_{q+1}, B_{q-1} = bt_{q-1} + M_{q-1} T_q
+        double tn0 = Tm0, tn1 = Tm1;
+        double a0, a1, p0 = 0.0, p1 = 0.0, n0 = 0.0, n1 = 0.0;
+        M2 A, Pq = {0, 0, 0, 0}, Nq = {0, 0, 0, 0};
+        if (m > 0) load6(cb + (size_t)(m - 1) * CS, NL, a0, a1, A);
+        if (m > 1) load6(cb + (size_t)(m - 2) * CS + 6 * NL, NL, p0, p1, Pq);
+        for (int q = m - 1; q >= 0; --q) {
+            if (q > 0) load6(cb + (size_t)(q - 1) * CS, NL, n0, n1, Nq);
+            double pp0 = 0.0, pp1 = 0.0;
+            M2 PP = {0, 0, 0, 0};
+            if (q > 1) load6(cb + (size_t)(q - 2) * CS + 6 * NL, NL, pp0, pp1, PP);
+            const double t0 = a0 + A.a * tn0 + A.b * tn1;
+            const double t1 = a1 + A.c * tn0 + A.d * tn1;
+            double *e = eb + (size_t)q * ES;
+            e[2 * NL] = tn0;
+            e[3 * NL] = tn1;
+            e[0] = q > 0 ? p0 + Pq.a * t0 + Pq.b * t1 : 0.0;
+            e[NL] = q > 0 ? p1 + Pq.c * t0 + Pq.d * t1 : 0.0;
+            tn0 = t0; tn1 = t1;
+            a0 = n0; a1 = n1; A = Nq;
+            p0 = pp0; p1 = pp1; Pq = PP;
+        }
+    } else {
+        // q = m..P-1: B_q = bb_q + S_q B_{q-1}, T_{q+1} = tt_{q+1} + R_{q+1} B_q
+        double bp0 = Bm0, bp1 = Bm1;
+        double a0, a1, r0 = 0.0, r1 = 0.0, n0 = 0.0, n1 = 0.0;
+        M2 A, Rq = {0, 0, 0, 0}, Nq = {0, 0, 0, 0};
+        load6(cb + (size_t)m * CS + 6 * NL, NL, a0, a1, A);
+        if (m + 1 < P) load6(cb + (size_t)(m + 1) * CS, NL, r0, r1, Rq);
+        for (int q = m; q < P; ++q) {
+            if (q + 1 < P) load6(cb + (size_t)(q + 1) * CS + 6 * NL, NL, n0, n1, Nq);
+            double rr0 = 0.0, rr1 = 0.0;
+            M2 RR = {0, 0, 0, 0};
+            if (q + 2 < P) load6(cb + (size_t)(q + 2) * CS, NL, rr0, rr1, RR);
+            const double b0 = a0 + A.a * bp0 + A.b * bp1;
+            const double b1 = a1 + A.c * bp0 + A.d * bp1;
+            double *e = eb + (size_t)q * ES;
+            e[0] = bp0;
+            e[NL] = bp1;
+            e[2 * NL] = q + 1 < P ? r0 + Rq.a * b0 + Rq.b * b1 : 0.0;
+            e[3 * NL] = q + 1 < P ? r1 + Rq.c * b0 + Rq.d * b1 : 0.0;
+            bp0 = b0; bp1 = b1;
+            a0 = n0; a1 = n1; A = Nq;
+            r0 = rr0; r1 = rr1; Rq = RR;
+        }
     }
 }
 
-__global__ void __launch_bounds__(64) k_chain(ChainParams c)
+__global__ void __launch_bounds__(128) k_chain(ChainParams c)
 {
-    const int line = blockIdx.x * 64 + threadIdx.x;
-    if (line < c.nlines) chain_body(c, line);
+    __shared__ ChainMeet mt;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    chain_line(c, blockIdx.x * 64 + lane, wave, lane, mt);
 }
 
 // Ensemble version: block -> (film, block of 64 lines); dir 0 chains the y sweep.
-__global__ void __launch_bounds__(64) k_chain_ens(EnsParams e, int dir)
+__global__ void __launch_bounds__(128) k_chain_ens(EnsParams e, int dir)
 {
+    __shared__ ChainMeet mt;
     const int f = e.items[2 * blockIdx.x], lb = e.items[2 * blockIdx.x + 1];
     const FilmState *s = e.state + f;
     if (!s->active) return;
     const FilmDesc d = e.desc[f];
     ChainParams c{dir == 0 ? d.nx : d.ny, dir == 0 ? d.Py : d.Px, e.rel + d.roff * NREL, e.chain + d.roff * NCHAIN,
                   e.ext + d.roff * NEXT};
-    const int line = lb * 64 + threadIdx.x;
-    if (line < c.nlines) chain_body(c, line);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    chain_line(c, lb * 64 + lane, wave, lane, mt);
 }
 
 // ------------------------------------------------------------------------------------
@@ -722,7 +951,7 @@ hipError_t launch_pass(int dir, bool solve, const PassParams &p, hipStream_t s)
 
 hipError_t launch_chain(const ChainParams &c, hipStream_t s)
 {
-    k_chain<<<dim3((c.nlines + 63) / 64), dim3(64), 0, s>>>(c);
+    k_chain<<<dim3((c.nlines + 63) / 64), dim3(128), 0, s>>>(c);
     return hipGetLastError();
 }
 
@@ -781,7 +1010,7 @@ hipError_t launch_pass_ens(int dir, bool solve, bool p32, const EnsParams &e, hi
 
 hipError_t launch_chain_ens(const EnsParams &e, int dir, hipStream_t s)
 {
-    k_chain_ens<<<dim3(e.nitems), dim3(64), 0, s>>>(e, dir);
+    k_chain_ens<<<dim3(e.nitems), dim3(128), 0, s>>>(e, dir);
     return hipGetLastError();
 }
 
