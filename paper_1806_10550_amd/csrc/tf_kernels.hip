@@ -345,6 +345,15 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
         const unsigned wf = wave_or(flags);
         if (lane == 0) { sRed[wave] = wm; sFlag[wave] = wf; }
     }
+    // solve pass: the tile's outer boundary values (from the chain) are loaded now, so
+    // that their latency overlaps the relation exchange
+    double l1 = 0.0, l2 = 0.0, r1 = 0.0, r2 = 0.0;
+    if (SOLVE && len > 0) {
+        const double *ex = p.ext + (size_t)qseg * NEXT * Nl;
+        const unsigned gc = (unsigned)min(max(gl, 0), Nl - 1);
+        l1 = ex[gc]; l2 = (ex + (size_t)Nl)[gc];
+        r1 = (ex + (size_t)2 * Nl)[gc]; r2 = (ex + (size_t)3 * Nl)[gc];
+    }
     __syncthreads(); // all sweeps done: the exchange area may be overwritten
     // the relations pass hands the records of waves 1.. to wave 0, which keeps its own
     const int xslot = SOLVE ? wave : wave - 1;
@@ -385,13 +394,7 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
 
     // ---- SOLVE: boundary values of this wave's sub-segment, then back-substitution
     double wl1 = 0.0, wl2 = 0.0, xr1 = 0.0, xr2 = 0.0;
-    if (len > 0) {
-        const double *ex = p.ext + (size_t)qseg * NEXT * Nl;
-        const unsigned gc = (unsigned)min(max(gl, 0), Nl - 1);
-        const double l1 = ex[gc], l2 = (ex + (size_t)Nl)[gc];
-        const double r1 = (ex + (size_t)2 * Nl)[gc], r2 = (ex + (size_t)3 * Nl)[gc];
-        chain_numeric(xch, lane, nsub, wave, l1, l2, r1, r2, wl1, wl2, xr1, xr2);
-    }
+    if (len > 0) chain_numeric(xch, lane, nsub, wave, l1, l2, r1, r2, wl1, wl2, xr1, xr2);
 
     if (DIR == 0) {
         // w goes straight from registers to memory: lanes cover consecutive x
@@ -514,23 +517,9 @@ __device__ __forceinline__ void load_rec(const double *r, size_t NL, double (&T)
         }
 }
 
-__device__ __forceinline__ void copy_rec(double (&dT)[2][5], double (&dB)[2][5], const double (&T)[2][5],
-                                         const double (&B)[2][5])
-{
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 5; ++j) { dT[i][j] = T[i][j]; dB[i][j] = B[i][j]; }
-}
-
 __device__ __forceinline__ void store6(double *w, size_t NL, double a0, double a1, const M2 &X)
 {
     w[0] = a0; w[NL] = a1; w[2 * NL] = X.a; w[3 * NL] = X.b; w[4 * NL] = X.c; w[5 * NL] = X.d;
-}
-
-__device__ __forceinline__ void load6(const double *w, size_t NL, double &a0, double &a1, M2 &X)
-{
-    a0 = w[0]; a1 = w[NL]; X.a = w[2 * NL]; X.b = w[3 * NL]; X.c = w[4 * NL]; X.d = w[5 * NL];
 }
 
 // Meeting record of one line: the forward wave leaves (bt_{m-1}, M_{m-1}), the backward
@@ -539,8 +528,15 @@ struct ChainMeet {
     double v[12][64];
 };
 
+// Records are loaded CHAIN_DEPTH segments ahead of their use (register rings indexed
+// statically through the unrolled inner loops): the chain is bound by memory latency.
+#ifndef CHAIN_DEPTH
+#define CHAIN_DEPTH 8
+#endif
+
 __device__ __forceinline__ void chain_line(const ChainParams &c, int line, int wave, int lane, ChainMeet &mt)
 {
+    constexpr int D = CHAIN_DEPTH;
     const size_t NL = (size_t)c.nlines;
     const size_t RS = (size_t)NREL * NL, CS = (size_t)NCHAIN * NL, ES = (size_t)NEXT * NL;
     const int P = c.P, m = P / 2;
@@ -548,78 +544,90 @@ __device__ __forceinline__ void chain_line(const ChainParams &c, int line, int w
     const double *rb = c.rel + line;
     double *cb = c.chain + line;
     double *eb = c.ext + line;
-    // records are loaded two segments ahead of their use to hide memory latency
-    double T[2][5], B[2][5], Tn[2][5], Bn[2][5], Tnn[2][5], Bnn[2][5];
-    double x0 = 0.0, x1 = 0.0;   // wave 0: bt_{q}; wave 1: tt_{q}
-    M2 X = {0, 0, 0, 0};         // wave 0: M_{q};  wave 1: R_{q}
-    if (wave == 0) {
-        // forward over q = 0..m-1: chain record (tau_q, N_q, bt_q, M_q)
-        if (live && m > 0) {
-            load_rec(rb, NL, T, B);
-            if (m > 1) load_rec(rb + RS, NL, Tn, Bn);
-            for (int q = 0; q < m; ++q) {
-                if (q + 2 < m) load_rec(rb + (size_t)(q + 2) * RS, NL, Tnn, Bnn);
-                const M2 Tl = {T[0][1], T[0][2], T[1][1], T[1][2]}, Tr = {T[0][3], T[0][4], T[1][3], T[1][4]};
-                const M2 Bl = {B[0][1], B[0][2], B[1][1], B[1][2]}, Br = {B[0][3], B[0][4], B[1][3], B[1][4]};
-                double tau0, tau1;
-                M2 N;
-                if (q == 0) {
-                    tau0 = T[0][0]; tau1 = T[1][0]; N = Tr;
-                    x0 = B[0][0]; x1 = B[1][0]; X = Br;
-                } else {
-                    const M2 K = inv_i_minus(mul(Tl, X));
-                    const double s0 = T[0][0] + Tl.a * x0 + Tl.b * x1;
-                    const double s1 = T[1][0] + Tl.c * x0 + Tl.d * x1;
-                    tau0 = K.a * s0 + K.b * s1;
-                    tau1 = K.c * s0 + K.d * s1;
-                    N = mul(K, Tr);
-                    const double v0 = x0 + X.a * tau0 + X.b * tau1;
-                    const double v1 = x1 + X.c * tau0 + X.d * tau1;
-                    const M2 BM = mul(mul(Bl, X), N);
-                    x0 = B[0][0] + Bl.a * v0 + Bl.b * v1;
-                    x1 = B[1][0] + Bl.c * v0 + Bl.d * v1;
-                    X = {BM.a + Br.a, BM.b + Br.b, BM.c + Br.c, BM.d + Br.d};
+    double x0 = 0.0, x1 = 0.0;   // wave 0: bt_q; wave 1: tt_q
+    M2 X = {0, 0, 0, 0};         // wave 0: M_q;  wave 1: R_q
+    if (live) {
+        double RT[D][2][5], RB[D][2][5];
+        if (wave == 0) {
+            // forward over q = 0..m-1: chain record (tau_q, N_q, bt_q, M_q)
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                if (j < m) load_rec(rb + (size_t)j * RS, NL, RT[j], RB[j]);
+            for (int q0 = 0; q0 < m; q0 += D) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const int q = q0 + j;
+                    if (q < m) {
+                        const double(&T)[2][5] = RT[j];
+                        const double(&B)[2][5] = RB[j];
+                        const M2 Tl = {T[0][1], T[0][2], T[1][1], T[1][2]}, Tr = {T[0][3], T[0][4], T[1][3], T[1][4]};
+                        const M2 Bl = {B[0][1], B[0][2], B[1][1], B[1][2]}, Br = {B[0][3], B[0][4], B[1][3], B[1][4]};
+                        double tau0, tau1;
+                        M2 N;
+                        if (q == 0) {
+                            tau0 = T[0][0]; tau1 = T[1][0]; N = Tr;
+                            x0 = B[0][0]; x1 = B[1][0]; X = Br;
+                        } else {
+                            const M2 K = inv_i_minus(mul(Tl, X));
+                            const double s0 = T[0][0] + Tl.a * x0 + Tl.b * x1;
+                            const double s1 = T[1][0] + Tl.c * x0 + Tl.d * x1;
+                            tau0 = K.a * s0 + K.b * s1;
+                            tau1 = K.c * s0 + K.d * s1;
+                            N = mul(K, Tr);
+                            const double v0 = x0 + X.a * tau0 + X.b * tau1;
+                            const double v1 = x1 + X.c * tau0 + X.d * tau1;
+                            const M2 BM = mul(mul(Bl, X), N);
+                            x0 = B[0][0] + Bl.a * v0 + Bl.b * v1;
+                            x1 = B[1][0] + Bl.c * v0 + Bl.d * v1;
+                            X = {BM.a + Br.a, BM.b + Br.b, BM.c + Br.c, BM.d + Br.d};
+                        }
+                        double *w = cb + (size_t)q * CS;
+                        store6(w, NL, tau0, tau1, N);
+                        store6(w + 6 * NL, NL, x0, x1, X);
+                        if (q + D < m) load_rec(rb + (size_t)(q + D) * RS, NL, RT[j], RB[j]);
+                    }
                 }
-                double *w = cb + (size_t)q * CS;
-                store6(w, NL, tau0, tau1, N);
-                store6(w + 6 * NL, NL, x0, x1, X);
-                copy_rec(T, B, Tn, Bn);
-                copy_rec(Tn, Bn, Tnn, Bnn);
             }
-        }
-    } else {
-        // backward over q = P-1..m: chain record (tt_q, R_q, bb_q, S_q)
-        if (live) {
-            load_rec(rb + (size_t)(P - 1) * RS, NL, T, B);
-            if (P - 2 >= m) load_rec(rb + (size_t)(P - 2) * RS, NL, Tn, Bn);
-            for (int q = P - 1; q >= m; --q) {
-                if (q - 2 >= m) load_rec(rb + (size_t)(q - 2) * RS, NL, Tnn, Bnn);
-                const M2 Tl = {T[0][1], T[0][2], T[1][1], T[1][2]}, Tr = {T[0][3], T[0][4], T[1][3], T[1][4]};
-                const M2 Bl = {B[0][1], B[0][2], B[1][1], B[1][2]}, Br = {B[0][3], B[0][4], B[1][3], B[1][4]};
-                double bb0, bb1;
-                M2 S;
-                if (q == P - 1) {
-                    bb0 = B[0][0]; bb1 = B[1][0]; S = Bl;
-                    x0 = T[0][0]; x1 = T[1][0]; X = Tl;
-                } else {
-                    const M2 K = inv_i_minus(mul(Br, X));
-                    const double s0 = B[0][0] + Br.a * x0 + Br.b * x1;
-                    const double s1 = B[1][0] + Br.c * x0 + Br.d * x1;
-                    bb0 = K.a * s0 + K.b * s1;
-                    bb1 = K.c * s0 + K.d * s1;
-                    S = mul(K, Bl);
-                    const double v0 = x0 + X.a * bb0 + X.b * bb1;
-                    const double v1 = x1 + X.c * bb0 + X.d * bb1;
-                    const M2 TRS = mul(mul(Tr, X), S);
-                    x0 = T[0][0] + Tr.a * v0 + Tr.b * v1;
-                    x1 = T[1][0] + Tr.c * v0 + Tr.d * v1;
-                    X = {TRS.a + Tl.a, TRS.b + Tl.b, TRS.c + Tl.c, TRS.d + Tl.d};
+        } else {
+            // backward over q = P-1..m: chain record (tt_q, R_q, bb_q, S_q)
+            const int nb = P - m;  // segments of this half; step i handles q = P-1-i
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                if (j < nb) load_rec(rb + (size_t)(P - 1 - j) * RS, NL, RT[j], RB[j]);
+            for (int i0 = 0; i0 < nb; i0 += D) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const int i = i0 + j, q = P - 1 - i;
+                    if (i < nb) {
+                        const double(&T)[2][5] = RT[j];
+                        const double(&B)[2][5] = RB[j];
+                        const M2 Tl = {T[0][1], T[0][2], T[1][1], T[1][2]}, Tr = {T[0][3], T[0][4], T[1][3], T[1][4]};
+                        const M2 Bl = {B[0][1], B[0][2], B[1][1], B[1][2]}, Br = {B[0][3], B[0][4], B[1][3], B[1][4]};
+                        double bb0, bb1;
+                        M2 S;
+                        if (i == 0) {
+                            bb0 = B[0][0]; bb1 = B[1][0]; S = Bl;
+                            x0 = T[0][0]; x1 = T[1][0]; X = Tl;
+                        } else {
+                            const M2 K = inv_i_minus(mul(Br, X));
+                            const double s0 = B[0][0] + Br.a * x0 + Br.b * x1;
+                            const double s1 = B[1][0] + Br.c * x0 + Br.d * x1;
+                            bb0 = K.a * s0 + K.b * s1;
+                            bb1 = K.c * s0 + K.d * s1;
+                            S = mul(K, Bl);
+                            const double v0 = x0 + X.a * bb0 + X.b * bb1;
+                            const double v1 = x1 + X.c * bb0 + X.d * bb1;
+                            const M2 TRS = mul(mul(Tr, X), S);
+                            x0 = T[0][0] + Tr.a * v0 + Tr.b * v1;
+                            x1 = T[1][0] + Tr.c * v0 + Tr.d * v1;
+                            X = {TRS.a + Tl.a, TRS.b + Tl.b, TRS.c + Tl.c, TRS.d + Tl.d};
+                        }
+                        double *w = cb + (size_t)q * CS;
+                        store6(w, NL, x0, x1, X);
+                        store6(w + 6 * NL, NL, bb0, bb1, S);
+                        if (i + D < nb) load_rec(rb + (size_t)(q - D) * RS, NL, RT[j], RB[j]);
+                    }
                 }
-                double *w = cb + (size_t)q * CS;
-                store6(w, NL, x0, x1, X);
-                store6(w + 6 * NL, NL, bb0, bb1, S);
-                copy_rec(T, B, Tn, Bn);
-                copy_rec(Tn, Bn, Tnn, Bnn);
             }
         }
     }
@@ -641,51 +649,72 @@ __device__ __forceinline__ void chain_line(const ChainParams &c, int line, int w
         Bm1 = K.c * s0 + K.d * s1;
     }
     const double Tm0 = tt0 + Rm.a * Bm0 + Rm.b * Bm1, Tm1 = tt1 + Rm.c * Bm0 + Rm.d * Bm1; // T_m
+    // substitution rings: (a, A) of segment q and its neighbour's (p, Pq)
+    double RA[D][6], RN[D][6];
+    auto ld6 = [&](const double *w, double (&o)[6]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) o[k] = w[(size_t)k * NL];
+    };
     if (wave == 0) {
         // q = m-1..0: T_q = tau_q + N_q T_{q+1}, B_{q-1} = bt_{q-1} + M_{q-1} T_q
         double tn0 = Tm0, tn1 = Tm1;
-        double a0, a1, p0 = 0.0, p1 = 0.0, n0 = 0.0, n1 = 0.0;
-        M2 A, Pq = {0, 0, 0, 0}, Nq = {0, 0, 0, 0};
-        if (m > 0) load6(cb + (size_t)(m - 1) * CS, NL, a0, a1, A);
-        if (m > 1) load6(cb + (size_t)(m - 2) * CS + 6 * NL, NL, p0, p1, Pq);
-        for (int q = m - 1; q >= 0; --q) {
-            if (q > 0) load6(cb + (size_t)(q - 1) * CS, NL, n0, n1, Nq);
-            double pp0 = 0.0, pp1 = 0.0;
-            M2 PP = {0, 0, 0, 0};
-            if (q > 1) load6(cb + (size_t)(q - 2) * CS + 6 * NL, NL, pp0, pp1, PP);
-            const double t0 = a0 + A.a * tn0 + A.b * tn1;
-            const double t1 = a1 + A.c * tn0 + A.d * tn1;
-            double *e = eb + (size_t)q * ES;
-            e[2 * NL] = tn0;
-            e[3 * NL] = tn1;
-            e[0] = q > 0 ? p0 + Pq.a * t0 + Pq.b * t1 : 0.0;
-            e[NL] = q > 0 ? p1 + Pq.c * t0 + Pq.d * t1 : 0.0;
-            tn0 = t0; tn1 = t1;
-            a0 = n0; a1 = n1; A = Nq;
-            p0 = pp0; p1 = pp1; Pq = PP;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int q = m - 1 - j;
+            if (q >= 0) ld6(cb + (size_t)q * CS, RA[j]);
+            if (q >= 1) ld6(cb + (size_t)(q - 1) * CS + 6 * NL, RN[j]);
+        }
+        for (int i0 = 0; i0 < m; i0 += D) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const int i = i0 + j, q = m - 1 - i;
+                if (i < m) {
+                    const double(&a)[6] = RA[j];
+                    const double(&pn)[6] = RN[j];
+                    const double t0 = a[0] + a[2] * tn0 + a[3] * tn1;
+                    const double t1 = a[1] + a[4] * tn0 + a[5] * tn1;
+                    double *e = eb + (size_t)q * ES;
+                    e[2 * NL] = tn0;
+                    e[3 * NL] = tn1;
+                    e[0] = q > 0 ? pn[0] + pn[2] * t0 + pn[3] * t1 : 0.0;
+                    e[NL] = q > 0 ? pn[1] + pn[4] * t0 + pn[5] * t1 : 0.0;
+                    tn0 = t0; tn1 = t1;
+                    const int qn = q - D;
+                    if (qn >= 0) ld6(cb + (size_t)qn * CS, RA[j]);
+                    if (qn >= 1) ld6(cb + (size_t)(qn - 1) * CS + 6 * NL, RN[j]);
+                }
+            }
         }
     } else {
         // q = m..P-1: B_q = bb_q + S_q B_{q-1}, T_{q+1} = tt_{q+1} + R_{q+1} B_q
         double bp0 = Bm0, bp1 = Bm1;
-        double a0, a1, r0 = 0.0, r1 = 0.0, n0 = 0.0, n1 = 0.0;
-        M2 A, Rq = {0, 0, 0, 0}, Nq = {0, 0, 0, 0};
-        load6(cb + (size_t)m * CS + 6 * NL, NL, a0, a1, A);
-        if (m + 1 < P) load6(cb + (size_t)(m + 1) * CS, NL, r0, r1, Rq);
-        for (int q = m; q < P; ++q) {
-            if (q + 1 < P) load6(cb + (size_t)(q + 1) * CS + 6 * NL, NL, n0, n1, Nq);
-            double rr0 = 0.0, rr1 = 0.0;
-            M2 RR = {0, 0, 0, 0};
-            if (q + 2 < P) load6(cb + (size_t)(q + 2) * CS, NL, rr0, rr1, RR);
-            const double b0 = a0 + A.a * bp0 + A.b * bp1;
-            const double b1 = a1 + A.c * bp0 + A.d * bp1;
-            double *e = eb + (size_t)q * ES;
-            e[0] = bp0;
-            e[NL] = bp1;
-            e[2 * NL] = q + 1 < P ? r0 + Rq.a * b0 + Rq.b * b1 : 0.0;
-            e[3 * NL] = q + 1 < P ? r1 + Rq.c * b0 + Rq.d * b1 : 0.0;
-            bp0 = b0; bp1 = b1;
-            a0 = n0; a1 = n1; A = Nq;
-            r0 = rr0; r1 = rr1; Rq = RR;
+        const int nb = P - m;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int q = m + j;
+            if (q < P) ld6(cb + (size_t)q * CS + 6 * NL, RA[j]);
+            if (q + 1 < P) ld6(cb + (size_t)(q + 1) * CS, RN[j]);
+        }
+        for (int i0 = 0; i0 < nb; i0 += D) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const int i = i0 + j, q = m + i;
+                if (i < nb) {
+                    const double(&a)[6] = RA[j];
+                    const double(&rn)[6] = RN[j];
+                    const double b0 = a[0] + a[2] * bp0 + a[3] * bp1;
+                    const double b1 = a[1] + a[4] * bp0 + a[5] * bp1;
+                    double *e = eb + (size_t)q * ES;
+                    e[0] = bp0;
+                    e[NL] = bp1;
+                    e[2 * NL] = q + 1 < P ? rn[0] + rn[2] * b0 + rn[3] * b1 : 0.0;
+                    e[3 * NL] = q + 1 < P ? rn[1] + rn[4] * b0 + rn[5] * b1 : 0.0;
+                    bp0 = b0; bp1 = b1;
+                    const int qn = q + D;
+                    if (qn < P) ld6(cb + (size_t)qn * CS + 6 * NL, RA[j]);
+                    if (qn + 1 < P) ld6(cb + (size_t)(qn + 1) * CS, RN[j]);
+                }
+            }
         }
     }
 }
