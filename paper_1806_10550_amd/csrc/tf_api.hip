@@ -14,6 +14,7 @@
 #include "../../include/thinfilm.h"
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -38,6 +39,7 @@ enum ProfKind { P_REL_Y, P_CHAIN_Y, P_SOLVE_Y, P_REL_X, P_CHAIN_X, P_SOLVE_X, P_
 const char *kProfNames = "relations_y,chain_y,solve_y,relations_x,chain_x,solve_x,rhs_theta,mass";
 
 constexpr int RES_SLOTS = 4;
+constexpr int RES_STRIDE = tf::RES_SPREAD * tf::RES_WORDS; // words per reduction slot
 
 } // namespace
 
@@ -116,6 +118,7 @@ tf::PassParams base_params(const tf_grid *g, double dt)
     P.K0 = 3.0 * P.ka * P.ids2;
     P.K1 = P.ka * g->M.Dn;
     P.M = g->M;
+    P.res_spread = tf::RES_SPREAD;
     return P;
 }
 
@@ -128,8 +131,8 @@ tf_status enqueue_iteration(tf_grid *g, const double *bnp, const double *uk, dou
     P.u = uk;
     P.rel = g->rel;
     P.ext = g->ext;
-    unsigned long long *res = g->res + (size_t)slot * tf::RES_WORDS;
-    unsigned long long *clr = g->res + (size_t)((slot + 2) % RES_SLOTS) * tf::RES_WORDS;
+    unsigned long long *res = g->res + (size_t)slot * RES_STRIDE;
+    unsigned long long *clr = g->res + (size_t)((slot + 2) % RES_SLOTS) * RES_STRIDE;
     tf_status st;
     // y sweep: (I + c J_y) w = -G(u_k)
     P.in2 = bnp;
@@ -159,16 +162,24 @@ tf_status enqueue_iteration(tf_grid *g, const double *bnp, const double *uk, dou
 
 tf_status read_result(tf_grid *g, int slot, double *e, double *r, int *flags)
 {
-    TF_HIP(hipMemcpyAsync(g->hres, g->res + (size_t)slot * tf::RES_WORDS, tf::RES_WORDS * sizeof(unsigned long long),
+    TF_HIP(hipMemcpyAsync(g->hres, g->res + (size_t)slot * RES_STRIDE, RES_STRIDE * sizeof(unsigned long long),
                           hipMemcpyDeviceToHost, g->stream));
     TF_HIP(hipStreamSynchronize(g->stream));
     if (g->prof) prof_flush(g);
+    // combine the copies: maxima of non-negative doubles compare as their bit patterns
+    unsigned long long em = 0, rm = 0, fl = 0;
+    for (int c = 0; c < tf::RES_SPREAD; ++c) {
+        const unsigned long long *w = g->hres + (size_t)c * tf::RES_WORDS;
+        em = std::max(em, w[tf::RES_EMAX]);
+        rm = std::max(rm, w[tf::RES_RMAX]);
+        fl |= w[tf::RES_FLAGS];
+    }
     double ev, rv;
-    std::memcpy(&ev, &g->hres[tf::RES_EMAX], sizeof(double));
-    std::memcpy(&rv, &g->hres[tf::RES_RMAX], sizeof(double));
+    std::memcpy(&ev, &em, sizeof(double));
+    std::memcpy(&rv, &rm, sizeof(double));
     *e = ev;
     *r = rv;
-    *flags = (int)g->hres[tf::RES_FLAGS];
+    *flags = (int)fl;
     return TF_OK;
 }
 
@@ -374,10 +385,10 @@ tf_status tf_create(int nx, int ny, double ds, void *stream, tf_grid **out)
               && hipMalloc(&g->ext, lines_seg * tf::NEXT * sizeof(double)) == hipSuccess
               && hipMalloc(&g->chain, lines_seg * tf::NCHAIN * sizeof(double)) == hipSuccess
               && hipMalloc(&g->partials, 4096 * 4 * sizeof(double)) == hipSuccess
-              && hipMalloc(&g->res, RES_SLOTS * tf::RES_WORDS * sizeof(unsigned long long)) == hipSuccess
-              && hipHostMalloc(&g->hres, tf::RES_WORDS * sizeof(unsigned long long), hipHostMallocDefault) == hipSuccess
+              && hipMalloc(&g->res, RES_SLOTS * RES_STRIDE * sizeof(unsigned long long)) == hipSuccess
+              && hipHostMalloc(&g->hres, RES_STRIDE * sizeof(unsigned long long), hipHostMallocDefault) == hipSuccess
               && hipHostMalloc(&g->hpart, 4096 * 4 * sizeof(double), hipHostMallocDefault) == hipSuccess;
-    if (ok) ok = hipMemsetAsync(g->res, 0, RES_SLOTS * tf::RES_WORDS * sizeof(unsigned long long), g->stream) == hipSuccess
+    if (ok) ok = hipMemsetAsync(g->res, 0, RES_SLOTS * RES_STRIDE * sizeof(unsigned long long), g->stream) == hipSuccess
                  && hipStreamSynchronize(g->stream) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();

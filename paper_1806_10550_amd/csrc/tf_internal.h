@@ -62,8 +62,9 @@ struct PassParams {
     double *out;        // y sweep: w; x sweep: u_{k+1}
     double *rel;        // [P][NREL][nlines]
     const double *ext;  // [P][NEXT][nlines]
-    unsigned long long *res;        // reduction slot {emax, rmax, flags, ...}
+    unsigned long long *res;        // reduction slot: res_spread records {emax, rmax, flags, ...}
     unsigned long long *res_clear;  // slot zeroed by block 0 (may be null)
+    int res_spread;                 // copies of the reduction record in a slot (>= 1)
     int tiles_x, tiles_y;
 };
 
@@ -75,6 +76,10 @@ struct ChainParams {
 };
 
 enum ResultWord { RES_EMAX = 0, RES_RMAX = 1, RES_FLAGS = 2, RES_WORDS = 8 };
+// A grid's reduction record is spread over RES_SPREAD copies (workgroup b updates copy
+// b % RES_SPREAD) so that the atomics of thousands of workgroups do not all meet at
+// one address; the host combines the copies.
+constexpr int RES_SPREAD = 64;
 
 // ---- ensemble of films packed in one buffer --------------------------------------------
 struct FilmDesc {          // constant per film

@@ -374,8 +374,9 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
             double m = 0.0;
             unsigned f = 0;
             for (int w = 0; w < NSUB; ++w) { m = fmax(m, sRed[w]); f |= sFlag[w]; }
-            atomicMax(&p.res[RES_RMAX], (unsigned long long)__double_as_longlong(m));
-            if (f) atomicOr(&p.res[RES_FLAGS], (unsigned long long)f);
+            unsigned long long *rs = p.res + (size_t)(blockIdx.x % p.res_spread) * RES_WORDS;
+            atomicMax(&rs[RES_RMAX], (unsigned long long)__double_as_longlong(m));
+            if (f) atomicOr(&rs[RES_FLAGS], (unsigned long long)f);
         }
         if (wave == 0 && owned) {
             Rel seg;
@@ -443,8 +444,9 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
             double m = 0.0;
             unsigned f = 0;
             for (int w = 0; w < NSUB; ++w) { m = fmax(m, sRed[w]); f |= sFlag[w]; }
-            atomicMax(&p.res[RES_EMAX], (unsigned long long)__double_as_longlong(m));
-            if (f) atomicOr(&p.res[RES_FLAGS], (unsigned long long)f);
+            unsigned long long *rs = p.res + (size_t)(blockIdx.x % p.res_spread) * RES_WORDS;
+            atomicMax(&rs[RES_EMAX], (unsigned long long)__double_as_longlong(m));
+            if (f) atomicOr(&rs[RES_FLAGS], (unsigned long long)f);
         }
     }
 }
@@ -460,7 +462,8 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
 template <int DIR, bool SOLVE, bool P32>
 __global__ void TF_PASS_ATTR k_pass(PassParams p)
 {
-    if (p.res_clear != nullptr && blockIdx.x == 0 && threadIdx.x < RES_WORDS) p.res_clear[threadIdx.x] = 0ull;
+    if (p.res_clear != nullptr && blockIdx.x == 0)
+        for (int i = threadIdx.x; i < p.res_spread * RES_WORDS; i += BLOCK) p.res_clear[i] = 0ull;
     const int t = xcd_tile(blockIdx.x, p.tiles_x * p.tiles_y);
     tile_body<DIR, SOLVE, P32>(p, t % p.tiles_x, t / p.tiles_x);
 }
@@ -491,6 +494,7 @@ __global__ void TF_PASS_ATTR k_pass_ens(EnsParams e)
     p.rel = e.rel + d.roff * NREL;
     p.ext = e.ext + d.roff * NEXT;
     p.res = s->red;
+    p.res_spread = 1;
     tile_body<DIR, SOLVE, P32>(p, tx, ty);
 }
 
