@@ -179,17 +179,20 @@ tf_status tf_jacobian_apply_t(tf_grid *g, const double *u, const double *mu, dou
  * to back (a, b, c, d, e = offsets -2..+2: row p of line l reads x at p-2..p+2 with
  * coefficients a..e at (p, l); entries reaching outside the line must be zero).
  * transposed != 0 solves with the transposed matrices. variant: 0 = partitioned
- * (64-cell segments, interface chain), 1 = one lane per line (Thomas), -1 = the
- * autotuned choice. No pivoting: the matrices must be LU-factorable without it.
- * Allocates and frees its own scratch; synchronises `stream`. */
+ * (64-cell segments, interface chain), 1 = one lane per line (Thomas), 2 = block cyclic
+ * reduction in LDS (one workgroup per line, n <= 2048), -1 = the autotuned choice. No
+ * pivoting: the matrices must be factorable without it. Allocates and frees its own
+ * scratch; synchronises `stream`. TF_EINVAL for bad sizes or variant 2 with n > 2048. */
 tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *rhs, double *x, int transposed,
                          int variant, void *stream);
-/* Time both variants on random diagonally dominant systems of the given length and
- * batch, remember the faster one for solves of similar shape (used by tf_adjoint_step
- * and tf_penta_solve with variant -1), and append a JSON line {arch, length, batch,
- * variant, ms} to cache_path (nullable). tf_autotune_load reads such a file (entries
- * of the current GPU architecture only). tf_autotune_choice returns the variant that
- * would be used (0 or 1). */
+/* Time the candidates -- partitioned; Thomas with 64, 128 and 256 lines per workgroup;
+ * block cyclic reduction (length <= 2048) -- on random diagonally dominant systems of
+ * the given length and batch (median of 5 timed runs after a warm-up), remember the
+ * fastest for solves of similar shape (used by tf_adjoint_step and tf_penta_solve with
+ * variant -1), and append a JSON line {arch, length, batch, variant, block, ms: {...}}
+ * to cache_path (nullable). tf_autotune_load reads such a file (entries of the current
+ * GPU architecture only). tf_autotune_choice returns the variant that would be used
+ * (0, 1 or 2). */
 tf_status tf_autotune(int length, int batch, const char *cache_path);
 tf_status tf_autotune_load(const char *cache_path);
 int tf_autotune_choice(int length, int batch);

@@ -231,21 +231,20 @@ __global__ void __launch_bounds__(BLOCK) k_sb_pass(SBParams P)
                     } else {
                         const double v = P.out[o] + x;
                         P.out[o] = v;
-                        xm = fmax(xm, fabs(x));
-                        om = fmax(om, fabs(v));
-                        if (x != x) xm = __builtin_nan("");
-                    }
+                        xm = max_nan(xm, fabs(x));
+                        om = max_nan(om, fabs(v));
+                            }
                 }
             }
         }
     }
     if (MODE == 1) {
-        const double wx = wave_max(xm), wo = wave_max(om);
+        const double wx = wave_max_nan(xm), wo = wave_max_nan(om);
         if (lane == 0) { sRed[wave][0] = wx; sRed[wave][1] = wo; }
         __syncthreads();
         if (tid == 0) {
             double a = 0.0, b = 0.0;
-            for (int w = 0; w < NSUB; ++w) { a = fmax(a, sRed[w][0]); b = fmax(b, sRed[w][1]); }
+            for (int w = 0; w < NSUB; ++w) { a = max_nan(a, sRed[w][0]); b = max_nan(b, sRed[w][1]); }
             atomicMax(&P.red[0], (unsigned long long)__double_as_longlong(a));
             atomicMax(&P.red[1], (unsigned long long)__double_as_longlong(b));
         }
@@ -253,11 +252,12 @@ __global__ void __launch_bounds__(BLOCK) k_sb_pass(SBParams P)
 }
 
 // Interleaved Thomas: one lane per line over the whole line, factors kept in a
-// position-major workspace (3 doubles per cell), then back-substitution.
+// position-major workspace (3 doubles per cell), then back-substitution. The block size
+// (64, 128 or 256 lines) is a tuning parameter.
 template <bool TRANS, int MODE>
-__global__ void __launch_bounds__(64) k_sb_thomas(SBParams P, double *work)
+__global__ void __launch_bounds__(256) k_sb_thomas(SBParams P, double *work)
 {
-    const int line = blockIdx.x * 64 + threadIdx.x;
+    const int line = blockIdx.x * blockDim.x + threadIdx.x;
     double xm = 0.0, om = 0.0;
     const size_t N = (size_t)P.nl * P.np;
     if (line < P.nl) {
@@ -287,17 +287,152 @@ __global__ void __launch_bounds__(64) k_sb_thomas(SBParams P, double *work)
             } else {
                 const double v = P.out[o] + x;
                 P.out[o] = v;
-                xm = fmax(xm, fabs(x));
-                om = fmax(om, fabs(v));
-                if (x != x) xm = __builtin_nan("");
+                xm = max_nan(xm, fabs(x));
+                om = max_nan(om, fabs(v));
             }
         }
     }
     if (MODE == 1) {
-        const double wx = wave_max(xm), wo = wave_max(om);
-        if (threadIdx.x == 0) {
+        const double wx = wave_max_nan(xm), wo = wave_max_nan(om);
+        if ((threadIdx.x & 63) == 0) {
             atomicMax(&P.red[0], (unsigned long long)__double_as_longlong(wx));
             atomicMax(&P.red[1], (unsigned long long)__double_as_longlong(wo));
+        }
+    }
+}
+
+// Block cyclic reduction in LDS. With X_i = (x_2i, x_2i+1) the pentadiagonal system of a
+// line is block tridiagonal in 2x2 blocks,
+//   A_i X_{i-1} + B_i X_i + C_i X_{i+1} = R_i,
+//   A_i = [a_2i b_2i; 0 a_2i+1], B_i = [c_2i d_2i; b_2i+1 c_2i+1], C_i = [e_2i 0; d_2i+1 e_2i+1]
+// (an odd line gets one identity row). Parallel cyclic reduction lets every block row
+// eliminate its neighbours at distance s = 1, 2, 4, ...,
+//   al = -A_i B_{i-s}^-1, ga = -C_i B_{i+s}^-1,
+//   A_i <- al A_{i-s}, C_i <- ga C_{i+s}, B_i <- B_i + al C_{i-s} + ga A_{i+s},
+//   R_i <- R_i + al R_{i-s} + ga R_{i+s},
+// until every block row stands alone: X_i = B_i^-1 R_i. One workgroup per line, the
+// whole line in LDS (lines of at most PCR_MAX cells). O(n log n) work, but log-depth:
+// it pays for few long lines.
+constexpr int PCR_MAX = 2048, PCR_THREADS = 256;
+constexpr int PCR_RPT = PCR_MAX / 2 / PCR_THREADS; // block rows per thread
+
+__device__ __forceinline__ M2 inv2(const M2 &x)
+{
+    const double r = rcp(x.a * x.d - x.b * x.c);
+    return {x.d * r, -x.b * r, -x.c * r, x.a * r};
+}
+__device__ __forceinline__ M2 add2(const M2 &x, const M2 &y) { return {x.a + y.a, x.b + y.b, x.c + y.c, x.d + y.d}; }
+
+template <bool TRANS, int MODE>
+__global__ void __launch_bounds__(PCR_THREADS) k_sb_pcr(SBParams P)
+{
+    constexpr int MB = PCR_MAX / 2;
+    __shared__ double sM[14][MB]; // A (4), B (4), C (4), R (2) per block row
+    __shared__ double sRed[PCR_THREADS / 64][2];
+    const int line = blockIdx.x, tid = threadIdx.x;
+    const int np = P.np, m = (np + 1) / 2;
+    const size_t N = (size_t)P.nl * np;
+    auto ld = [&](int i, M2 &A, M2 &B, M2 &C, double &r0, double &r1) {
+        A = {sM[0][i], sM[1][i], sM[2][i], sM[3][i]};
+        B = {sM[4][i], sM[5][i], sM[6][i], sM[7][i]};
+        C = {sM[8][i], sM[9][i], sM[10][i], sM[11][i]};
+        r0 = sM[12][i];
+        r1 = sM[13][i];
+    };
+    auto st = [&](int i, const M2 &A, const M2 &B, const M2 &C, double r0, double r1) {
+        sM[0][i] = A.a; sM[1][i] = A.b; sM[2][i] = A.c; sM[3][i] = A.d;
+        sM[4][i] = B.a; sM[5][i] = B.b; sM[6][i] = B.c; sM[7][i] = B.d;
+        sM[8][i] = C.a; sM[9][i] = C.b; sM[10][i] = C.c; sM[11][i] = C.d;
+        sM[12][i] = r0; sM[13][i] = r1;
+    };
+    for (int i = tid; i < m; i += PCR_THREADS) {
+        double a0, b0, c0, d0, e0, a1 = 0.0, b1 = 0.0, c1 = 1.0, d1 = 0.0, e1 = 0.0, r1 = 0.0;
+        load_band_row<TRANS>(P.bands, N, P.nl, np, 2 * i, line, a0, b0, c0, d0, e0);
+        const double r0 = P.rhs[(size_t)(2 * i) * P.nl + line];
+        if (2 * i + 1 < np) {
+            load_band_row<TRANS>(P.bands, N, P.nl, np, 2 * i + 1, line, a1, b1, c1, d1, e1);
+            r1 = P.rhs[(size_t)(2 * i + 1) * P.nl + line];
+        }
+        st(i, {a0, b0, 0.0, a1}, {c0, d0, b1, c1}, {e0, 0.0, d1, e1}, r0, r1);
+    }
+    __syncthreads();
+    for (int s = 1; s < m; s <<= 1) {
+        M2 nA[PCR_RPT], nB[PCR_RPT], nC[PCR_RPT];
+        double nr0[PCR_RPT], nr1[PCR_RPT];
+#pragma unroll
+        for (int k = 0; k < PCR_RPT; ++k) {
+            const int i = tid + k * PCR_THREADS;
+            if (i < m) {
+                M2 A, B, C;
+                double r0, r1;
+                ld(i, A, B, C, r0, r1);
+                M2 oA = {0, 0, 0, 0}, oC = {0, 0, 0, 0};
+                if (i - s >= 0) {
+                    M2 Al, Bl, Cl;
+                    double l0, l1;
+                    ld(i - s, Al, Bl, Cl, l0, l1);
+                    const M2 al = mul(A, inv2(Bl));
+                    oA = {-(al.a * Al.a + al.b * Al.c), -(al.a * Al.b + al.b * Al.d),
+                          -(al.c * Al.a + al.d * Al.c), -(al.c * Al.b + al.d * Al.d)};
+                    const M2 t = mul(al, Cl);
+                    B = {B.a - t.a, B.b - t.b, B.c - t.c, B.d - t.d};
+                    r0 -= al.a * l0 + al.b * l1;
+                    r1 -= al.c * l0 + al.d * l1;
+                }
+                if (i + s < m) {
+                    M2 Ar, Br, Cr;
+                    double q0, q1;
+                    ld(i + s, Ar, Br, Cr, q0, q1);
+                    const M2 ga = mul(C, inv2(Br));
+                    oC = {-(ga.a * Cr.a + ga.b * Cr.c), -(ga.a * Cr.b + ga.b * Cr.d),
+                          -(ga.c * Cr.a + ga.d * Cr.c), -(ga.c * Cr.b + ga.d * Cr.d)};
+                    const M2 t = mul(ga, Ar);
+                    B = {B.a - t.a, B.b - t.b, B.c - t.c, B.d - t.d};
+                    r0 -= ga.a * q0 + ga.b * q1;
+                    r1 -= ga.c * q0 + ga.d * q1;
+                }
+                nA[k] = oA; nB[k] = B; nC[k] = oC; nr0[k] = r0; nr1[k] = r1;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PCR_RPT; ++k) {
+            const int i = tid + k * PCR_THREADS;
+            if (i < m) st(i, nA[k], nB[k], nC[k], nr0[k], nr1[k]);
+        }
+        __syncthreads();
+    }
+    double xm = 0.0, om = 0.0;
+    for (int i = tid; i < m; i += PCR_THREADS) {
+        M2 A, B, C;
+        double r0, r1;
+        ld(i, A, B, C, r0, r1);
+        const M2 Bi = inv2(B);
+        const double x[2] = {Bi.a * r0 + Bi.b * r1, Bi.c * r0 + Bi.d * r1};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int p = 2 * i + h;
+            if (p >= np) break;
+            const size_t o = (size_t)p * P.nl + line;
+            if (MODE == 0) {
+                P.out[o] = x[h];
+            } else {
+                const double v = P.out[o] + x[h];
+                P.out[o] = v;
+                xm = max_nan(xm, fabs(x[h]));
+                om = max_nan(om, fabs(v));
+            }
+        }
+    }
+    if (MODE == 1) {
+        const double wx = wave_max_nan(xm), wo = wave_max_nan(om);
+        if ((tid & 63) == 0) { sRed[tid >> 6][0] = wx; sRed[tid >> 6][1] = wo; }
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0.0, b = 0.0;
+            for (int w = 0; w < PCR_THREADS / 64; ++w) { a = max_nan(a, sRed[w][0]); b = max_nan(b, sRed[w][1]); }
+            atomicMax(&P.red[0], (unsigned long long)__double_as_longlong(a));
+            atomicMax(&P.red[1], (unsigned long long)__double_as_longlong(b));
         }
     }
 }
@@ -436,12 +571,18 @@ tf_status afail(tf_status s, const std::string &msg)
         if (e_ != hipSuccess) return afail(TF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-enum Variant { V_PARTITIONED = 0, V_THOMAS = 1 };
-const char *kVariantNames[] = {"partitioned", "thomas"};
+enum Variant { V_PARTITIONED = 0, V_THOMAS = 1, V_PCR = 2, N_VARIANTS = 3 };
+const char *kVariantNames[] = {"partitioned", "thomas", "pcr"};
+
+// A solver choice: the variant and, for Thomas, the workgroup size (lines per block).
+struct Choice {
+    int variant = V_PARTITIONED;
+    int block = 64;
+};
 
 struct TuneTable {
     std::mutex mu;
-    std::map<std::pair<int, int>, int> best; // (length, batch) -> variant
+    std::map<std::pair<int, int>, Choice> best; // (length, batch) -> choice
 };
 TuneTable &tune_table()
 {
@@ -449,33 +590,47 @@ TuneTable &tune_table()
     return t;
 }
 
-// variant for a batch of `nl` lines of length `np`: the autotuned entry with the
-// nearest (log-distance) key, else a heuristic (one lane per line only pays when the
-// lines alone fill the GPU)
-int pick_variant(int np, int nl)
+// choice for a batch of `nl` lines of length `np`: the autotuned entry with the nearest
+// (log-distance) key, else a heuristic (one lane per line only pays when the lines
+// alone fill the GPU). Cyclic reduction is only used for lines that fit in LDS.
+Choice pick_variant(int np, int nl)
 {
     TuneTable &t = tune_table();
     std::lock_guard<std::mutex> lk(t.mu);
     double best_d = 1e30;
-    int v = -1;
+    Choice c;
+    bool found = false;
     for (auto &kv : t.best) {
         const double d = std::fabs(std::log((double)kv.first.first / np)) + std::fabs(std::log((double)kv.first.second / nl));
-        if (d < best_d) { best_d = d; v = kv.second; }
+        if (d < best_d) { best_d = d; c = kv.second; found = true; }
     }
-    if (v >= 0 && best_d < 0.7) return v;
-    return nl >= 65536 ? V_THOMAS : V_PARTITIONED;
+    if (found && best_d < 0.7 && !(c.variant == V_PCR && np > tf::PCR_MAX)) return c;
+    c.variant = nl >= 65536 ? V_THOMAS : V_PARTITIONED;
+    c.block = 64;
+    return c;
 }
 
 struct Scratch {
     double *rel = nullptr, *ext = nullptr, *chain = nullptr, *work = nullptr;
 };
 
-tf_status sb_solve(int variant, bool trans, int mode, int nl, int np, const double *bands, const double *rhs,
+tf_status sb_solve(Choice ch, bool trans, int mode, int nl, int np, const double *bands, const double *rhs,
                    double *out, unsigned long long *red, const Scratch &S, hipStream_t s)
 {
     tf::SBParams P{nl, np, bands, rhs, out, S.rel, S.ext, red};
-    if (variant == V_THOMAS) {
-        const dim3 g((nl + 63) / 64), b(64);
+    if (ch.variant == V_PCR) {
+        if (np > tf::PCR_MAX) return afail(TF_EINVAL, "cyclic reduction needs lines of at most 2048 cells");
+        const dim3 g(nl), b(tf::PCR_THREADS);
+        if (!trans && mode == 0) tf::k_sb_pcr<false, 0><<<g, b, 0, s>>>(P);
+        else if (!trans) tf::k_sb_pcr<false, 1><<<g, b, 0, s>>>(P);
+        else if (mode == 0) tf::k_sb_pcr<true, 0><<<g, b, 0, s>>>(P);
+        else tf::k_sb_pcr<true, 1><<<g, b, 0, s>>>(P);
+        TF_AHIP(hipGetLastError());
+        return TF_OK;
+    }
+    if (ch.variant == V_THOMAS) {
+        const int bs = ch.block == 128 || ch.block == 256 ? ch.block : 64;
+        const dim3 g((nl + bs - 1) / bs), b(bs);
         if (!trans && mode == 0) tf::k_sb_thomas<false, 0><<<g, b, 0, s>>>(P, S.work);
         else if (!trans) tf::k_sb_thomas<false, 1><<<g, b, 0, s>>>(P, S.work);
         else if (mode == 0) tf::k_sb_thomas<true, 0><<<g, b, 0, s>>>(P, S.work);
@@ -654,7 +809,7 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
         TF_AHIP(hipGetLastError());
     }
     Scratch S{v.rel, v.ext, v.chain, B.work};
-    const int vx = pick_variant(nx, ny), vy = pick_variant(ny, nx);
+    const Choice vx = pick_variant(nx, ny), vy = pick_variant(ny, nx);
     TF_AHIP(hipMemsetAsync(B.mu, 0, N * sizeof(double), s));
     int it;
     bool conv = false;
@@ -725,8 +880,9 @@ tf_status tf_jacobian_apply_t(tf_grid *g, const double *u, const double *mu, dou
 tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *rhs, double *x, int transposed,
                          int variant, void *stream)
 {
-    if (nlines < 1 || n < 2 || bands == nullptr || rhs == nullptr || x == nullptr || variant < -1 || variant > 1)
+    if (nlines < 1 || n < 2 || bands == nullptr || rhs == nullptr || x == nullptr || variant < -1 || variant > 2)
         return afail(TF_EINVAL, "bad argument");
+    if (variant == V_PCR && n > tf::PCR_MAX) return afail(TF_EINVAL, "cyclic reduction needs n <= 2048");
     hipStream_t s = (hipStream_t)stream;
     const size_t recs = (size_t)tf::seg_count(n) * nlines;
     Scratch S;
@@ -737,8 +893,10 @@ tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *r
     tf_status st = TF_OK;
     if (!ok) st = afail(TF_ENOMEM, "scratch allocation failed");
     if (st == TF_OK) {
-        const int v = variant < 0 ? pick_variant(n, nlines) : variant;
-        st = sb_solve(v, transposed != 0, 0, nlines, n, bands, rhs, x, nullptr, S, s);
+        Choice c;
+        if (variant < 0) c = pick_variant(n, nlines);
+        else c.variant = variant;
+        st = sb_solve(c, transposed != 0, 0, nlines, n, bands, rhs, x, nullptr, S, s);
         if (st == TF_OK && hipStreamSynchronize(s) != hipSuccess) st = afail(TF_EDEVICE, "synchronize failed");
     }
     (void)hipFree(S.rel);
@@ -764,17 +922,31 @@ tf_status tf_autotune(int length, int batch, const char *cache_path)
               && hipMalloc(&S.chain, recs * tf::NCHAIN * sizeof(double)) == hipSuccess
               && hipMalloc(&S.work, 3 * N * sizeof(double)) == hipSuccess;
     tf_status st = ok ? TF_OK : afail(TF_ENOMEM, "autotune allocation failed");
-    double ms[2] = {0.0, 0.0};
+    // candidates: partitioned; Thomas with 64, 128, 256 lines per block; cyclic reduction
+    // (lines of at most PCR_MAX cells)
+    std::vector<Choice> cands;
+    std::vector<std::string> names;
+    cands.push_back({V_PARTITIONED, 64});
+    names.push_back("partitioned");
+    for (int bs : {64, 128, 256}) {
+        cands.push_back({V_THOMAS, bs});
+        names.push_back("thomas/" + std::to_string(bs));
+    }
+    if (length <= tf::PCR_MAX) {
+        cands.push_back({V_PCR, tf::PCR_THREADS});
+        names.push_back("pcr");
+    }
+    std::vector<double> ms(cands.size(), 1e30);
     if (st == TF_OK) {
         tf::k_fill_test<<<dim3(1024), dim3(256), 0, s>>>(N, bands, rhs);
         hipEvent_t a, b;
         (void)hipEventCreate(&a);
         (void)hipEventCreate(&b);
-        for (int v = 0; v < 2 && st == TF_OK; ++v) {
+        for (size_t v = 0; v < cands.size() && st == TF_OK; ++v) {
             std::vector<float> t;
             for (int r = 0; r < 6 && st == TF_OK; ++r) {
                 (void)hipEventRecord(a, s);
-                st = sb_solve(v, false, 0, batch, length, bands, rhs, x, nullptr, S, s);
+                st = sb_solve(cands[v], false, 0, batch, length, bands, rhs, x, nullptr, S, s);
                 (void)hipEventRecord(b, s);
                 (void)hipEventSynchronize(b);
                 float e = 0.0f;
@@ -796,23 +968,29 @@ tf_status tf_autotune(int length, int batch, const char *cache_path)
     (void)hipFree(S.work);
     if (s) (void)hipStreamDestroy(s);
     if (st != TF_OK) return st;
-    const int best = ms[0] <= ms[1] ? V_PARTITIONED : V_THOMAS;
+    size_t best = 0;
+    for (size_t v = 1; v < cands.size(); ++v)
+        if (ms[v] < ms[best]) best = v;
     {
         TuneTable &t = tune_table();
         std::lock_guard<std::mutex> lk(t.mu);
-        t.best[{length, batch}] = best;
+        t.best[{length, batch}] = cands[best];
     }
     if (cache_path != nullptr && cache_path[0] != '\0') {
-        // one JSON object per line: {"arch", "length", "batch", "variant", "ms": {...}}
+        // one JSON object per line: {"arch", "length", "batch", "variant", "block", "ms": {...}}
         std::ofstream f(cache_path, std::ios::app);
         if (!f) return afail(TF_EINVAL, std::string("cannot write ") + cache_path);
-        char line[512];
-        std::snprintf(line, sizeof line,
-                      "{\"arch\": \"%s\", \"length\": %d, \"batch\": %d, \"variant\": \"%s\", \"ms\": {\"%s\": %.6f, "
-                      "\"%s\": %.6f}}\n",
-                      arch_name().c_str(), length, batch, kVariantNames[best], kVariantNames[0], ms[0],
-                      kVariantNames[1], ms[1]);
-        f << line;
+        std::ostringstream o;
+        o << "{\"arch\": \"" << arch_name() << "\", \"length\": " << length << ", \"batch\": " << batch
+          << ", \"variant\": \"" << kVariantNames[cands[best].variant] << "\", \"block\": " << cands[best].block
+          << ", \"ms\": {";
+        char buf[64];
+        for (size_t v = 0; v < cands.size(); ++v) {
+            std::snprintf(buf, sizeof buf, "%.6f", ms[v]);
+            o << (v ? ", " : "") << "\"" << names[v] << "\": " << buf;
+        }
+        o << "}}\n";
+        f << o.str();
     }
     return TF_OK;
 }
@@ -842,14 +1020,17 @@ tf_status tf_autotune_load(const char *cache_path)
             return line.substr(q, e - q);
         };
         if (field("arch") != arch) continue;
-        const std::string L = field("length"), Bt = field("batch"), V = field("variant");
+        const std::string L = field("length"), Bt = field("batch"), V = field("variant"), Bs = field("block");
         if (L.empty() || Bt.empty()) continue;
-        t.best[{std::stoi(L), std::stoi(Bt)}] = V == "thomas" ? V_THOMAS : V_PARTITIONED;
+        Choice c;
+        c.variant = V == "thomas" ? V_THOMAS : (V == "pcr" ? V_PCR : V_PARTITIONED);
+        c.block = Bs.empty() ? 64 : std::stoi(Bs);
+        t.best[{std::stoi(L), std::stoi(Bt)}] = c;
         ++loaded;
     }
     return loaded > 0 ? TF_OK : afail(TF_EINVAL, "no entries for this GPU architecture in the cache");
 }
 
-int tf_autotune_choice(int length, int batch) { return pick_variant(length, batch); }
+int tf_autotune_choice(int length, int batch) { return pick_variant(length, batch).variant; }
 
 } // extern "C"

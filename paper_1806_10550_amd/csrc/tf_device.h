@@ -284,6 +284,14 @@ __device__ __forceinline__ double wave_max(double v)
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
 }
+// Maximum that keeps a NaN (fmax drops it): used where a NaN must reach the host.
+__device__ __forceinline__ double max_nan(double a, double b) { return (b != b || b > a) ? b : a; }
+__device__ __forceinline__ double wave_max_nan(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max_nan(v, __shfl_xor(v, o));
+    return v;
+}
 __device__ __forceinline__ unsigned wave_or(unsigned v)
 {
 #pragma unroll

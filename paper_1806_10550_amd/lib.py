@@ -303,7 +303,8 @@ class Ensemble:
         return info.as_dict()
 
 
-VARIANTS = {"auto": -1, "partitioned": 0, "thomas": 1}
+VARIANTS = {"auto": -1, "partitioned": 0, "thomas": 1, "pcr": 2}
+VARIANT_NAMES = ["partitioned", "thomas", "pcr"]
 
 
 def penta_solve(bands, rhs, x, transposed=False, variant="auto", stream=None):
@@ -319,7 +320,7 @@ def penta_solve(bands, rhs, x, transposed=False, variant="auto", stream=None):
 
 def autotune(length: int, batch: int, cache_path: str | None = None) -> str:
     _check(lib().tf_autotune(int(length), int(batch), cache_path.encode() if cache_path else None))
-    return ["partitioned", "thomas"][lib().tf_autotune_choice(int(length), int(batch))]
+    return VARIANT_NAMES[lib().tf_autotune_choice(int(length), int(batch))]
 
 
 def autotune_load(cache_path: str) -> None:
@@ -327,4 +328,4 @@ def autotune_load(cache_path: str) -> None:
 
 
 def autotune_choice(length: int, batch: int) -> str:
-    return ["partitioned", "thomas"][lib().tf_autotune_choice(int(length), int(batch))]
+    return VARIANT_NAMES[lib().tf_autotune_choice(int(length), int(batch))]

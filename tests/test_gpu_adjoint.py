@@ -51,9 +51,9 @@ def _bands(n, nl, seed, dominant=True):
     return b
 
 
-@pytest.mark.parametrize("n,nl", [(2, 3), (5, 7), (64, 64), (65, 130), (200, 33), (1000, 5)])
+@pytest.mark.parametrize("n,nl", [(2, 3), (5, 7), (64, 64), (65, 130), (200, 33), (1000, 5), (2047, 3)])
 @pytest.mark.parametrize("transposed", [False, True])
-@pytest.mark.parametrize("variant", ["partitioned", "thomas"])
+@pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr"])
 def test_penta_solve_matches_oracle(orc, n, nl, transposed, variant):
     b = _bands(n, nl, seed=n * 7 + nl)
     rhs = np.random.default_rng(n + nl).standard_normal((n, nl))
@@ -68,7 +68,7 @@ def test_penta_solve_matches_oracle(orc, n, nl, transposed, variant):
         assert np.max(np.abs(got[:, l] - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), l
 
 
-@pytest.mark.parametrize("variant", ["partitioned", "thomas"])
+@pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr"])
 def test_penta_solve_on_model_bands(orc, variant):
     """Real (I + c J_x) systems of a noisy film (not diagonally dominant)."""
     nx, ny = 300, 40
@@ -159,9 +159,27 @@ def test_rollout_gradient_matches_oracle_adjoint(orc):
 def test_autotune_cache_roundtrip(tmp_path):
     path = str(tmp_path / "tune.jsonl")
     choice = autotune(512, 512, path)
-    assert choice in ("partitioned", "thomas")
+    assert choice in ("partitioned", "thomas", "pcr")
     rec = json.loads(open(path).read().strip().splitlines()[-1])
     assert rec["length"] == 512 and rec["batch"] == 512 and rec["variant"] == choice
-    assert set(rec["ms"]) == {"partitioned", "thomas"} and all(math.isfinite(v) for v in rec["ms"].values())
+    assert set(rec["ms"]) == {"partitioned", "thomas/64", "thomas/128", "thomas/256", "pcr"}
+    assert all(math.isfinite(v) for v in rec["ms"].values())
+    best = min(rec["ms"], key=rec["ms"].get)
+    assert best.split("/")[0] == choice
+    if choice == "thomas":
+        assert rec["block"] == int(best.split("/")[1])
     autotune_load(path)
     assert autotune_choice(512, 512) == choice
+    # long lines: no cyclic reduction candidate
+    autotune(4096, 8, path)
+    rec = json.loads(open(path).read().strip().splitlines()[-1])
+    assert "pcr" not in rec["ms"] and rec["length"] == 4096
+
+
+def test_pcr_rejects_long_lines():
+    n, nl = 2050, 2
+    b = gpu(_bands(n, nl, seed=1))
+    rhs = gpu(np.ones((n, nl)))
+    x = torch.empty((n, nl), dtype=torch.float64, device=DEV)
+    with pytest.raises(Exception):
+        penta_solve(b, rhs, x, variant="pcr")
