@@ -150,8 +150,8 @@ def bench_adjoint(args):
     import torch
 
     from paper_1806_10550_amd import synth
-    from paper_1806_10550_amd.adjoint import rollout
-    from paper_1806_10550_amd.lib import Grid
+    from paper_1806_10550_amd.adjoint import Rollout, rollout
+    from paper_1806_10550_amd.lib import Grid, autotune_choice
 
     cfg = synth.CONFIGS["adjoint512"]
     n, dt, steps = cfg.n, cfg.dt, args.steps
@@ -188,6 +188,8 @@ def bench_adjoint(args):
                                   f"{steps} steps, checkpoints every {cfg.extra['checkpoint_every']}, "
                                   f"loss 0.5||h(T)-h_target||^2"},
            "forward_s": t_fwd, "forward_plus_adjoint_s": t_adj, "forward_newton_iters": fwd_iters,
+           "richardson_iters": Rollout.stats["richardson_iters"],
+           "solver_variant": autotune_choice(n, n, transposed=True),
            "loss": loss.item(), "grad_p0_norm": p0.grad.norm().item(), "grad_kappa": kap.grad.item()}
     print(json.dumps(out), flush=True)
 

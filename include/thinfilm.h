@@ -187,15 +187,16 @@ tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *r
                          int variant, void *stream);
 /* Time the candidates -- partitioned; Thomas with 64, 128 and 256 lines per workgroup;
  * block cyclic reduction (length <= 2048) -- on random diagonally dominant systems of
- * the given length and batch (median of 5 timed runs after a warm-up), remember the
- * fastest for solves of similar shape (used by tf_adjoint_step and tf_penta_solve with
- * variant -1), and append a JSON line {arch, length, batch, variant, block, ms: {...}}
- * to cache_path (nullable). tf_autotune_load reads such a file (entries of the current
- * GPU architecture only). tf_autotune_choice returns the variant that would be used
- * (0, 1 or 2). */
-tf_status tf_autotune(int length, int batch, const char *cache_path);
+ * the given length and batch, plain (transposed = 0) or transposed solves (median of 5
+ * timed runs after a warm-up), remember the fastest for solves of the same kind and
+ * similar shape (used by tf_adjoint_step, whose solves are transposed, and by
+ * tf_penta_solve with variant -1), and append a JSON line {arch, length, batch,
+ * transposed, variant, block, ms: {...}} to cache_path (nullable). tf_autotune_load
+ * reads such a file (entries of the current GPU architecture only; TF_EINVAL if there
+ * are none). tf_autotune_choice returns the variant that would be used (0, 1 or 2). */
+tf_status tf_autotune(int length, int batch, int transposed, const char *cache_path);
 tf_status tf_autotune_load(const char *cache_path);
-int tf_autotune_choice(int length, int batch);
+int tf_autotune_choice(int length, int batch, int transposed);
 
 /* Description of the calling thread's most recent error (never NULL). */
 const char *tf_last_error(void);

@@ -11,10 +11,13 @@ from __future__ import annotations
 
 import torch
 
-from .lib import Grid
+from .lib import Grid, load_shipped_tuning
 
 
 class Rollout(torch.autograd.Function):
+    # totals of the last backward pass: adjoint steps and Richardson iterations
+    stats = {"adjoint_steps": 0, "richardson_iters": 0}
+
     @staticmethod
     def forward(ctx, p0, kappa, h_base, nsteps: int, dt: float, ds: float, checkpoint_every: int = 20,
                 tol: float = 1e-10, adj_tol: float = 1e-13, b: float = 0.1, n: int = 3, m: int = 2):
@@ -39,6 +42,8 @@ class Rollout(torch.autograd.Function):
     def backward(ctx, grad_h):
         g = ctx.grid
         nsteps, dt, K, adj_tol = ctx.cfg
+        load_shipped_tuning()  # solver variants tuned for this GPU, if shipped
+        steps = iters = 0
         lam = grad_h.detach().contiguous().clone()
         gk = 0.0
         work = torch.empty_like(lam)
@@ -53,8 +58,11 @@ class Rollout(torch.autograd.Function):
                 g.step(dt)
                 states.append(work.clone())
             for s in range(end - start - 1, -1, -1):
-                c, _ = g.adjoint_step(states[s], states[s + 1], dt, lam, tol=adj_tol)
+                c, it = g.adjoint_step(states[s], states[s + 1], dt, lam, tol=adj_tol)
                 gk += c
+                steps += 1
+                iters += it
+        Rollout.stats = {"adjoint_steps": steps, "richardson_iters": iters}
         grad_k = torch.full(ctx.kappa_shape, gk, dtype=torch.float64, device=lam.device)
         return lam, grad_k, None, None, None, None, None, None, None, None, None, None
 

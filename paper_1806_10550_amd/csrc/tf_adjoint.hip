@@ -580,9 +580,16 @@ struct Choice {
     int block = 64;
 };
 
+struct TuneKey {
+    int length, batch, transposed;
+    bool operator<(const TuneKey &o) const
+    {
+        return length != o.length ? length < o.length : (batch != o.batch ? batch < o.batch : transposed < o.transposed);
+    }
+};
 struct TuneTable {
     std::mutex mu;
-    std::map<std::pair<int, int>, Choice> best; // (length, batch) -> choice
+    std::map<TuneKey, Choice> best; // (length, batch, transposed) -> choice
 };
 TuneTable &tune_table()
 {
@@ -590,10 +597,11 @@ TuneTable &tune_table()
     return t;
 }
 
-// choice for a batch of `nl` lines of length `np`: the autotuned entry with the nearest
-// (log-distance) key, else a heuristic (one lane per line only pays when the lines
-// alone fill the GPU). Cyclic reduction is only used for lines that fit in LDS.
-Choice pick_variant(int np, int nl)
+// choice for a batch of `nl` lines of length `np` (plain or transposed solves): the
+// autotuned entry of the same kind with the nearest (log-distance) shape, else a
+// heuristic (one lane per line only pays when the lines alone fill the GPU). Cyclic
+// reduction is only used for lines that fit in LDS.
+Choice pick_variant(int np, int nl, bool trans)
 {
     TuneTable &t = tune_table();
     std::lock_guard<std::mutex> lk(t.mu);
@@ -601,7 +609,8 @@ Choice pick_variant(int np, int nl)
     Choice c;
     bool found = false;
     for (auto &kv : t.best) {
-        const double d = std::fabs(std::log((double)kv.first.first / np)) + std::fabs(std::log((double)kv.first.second / nl));
+        if (kv.first.transposed != (int)trans) continue;
+        const double d = std::fabs(std::log((double)kv.first.length / np)) + std::fabs(std::log((double)kv.first.batch / nl));
         if (d < best_d) { best_d = d; c = kv.second; found = true; }
     }
     if (found && best_d < 0.7 && !(c.variant == V_PCR && np > tf::PCR_MAX)) return c;
@@ -809,7 +818,7 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
         TF_AHIP(hipGetLastError());
     }
     Scratch S{v.rel, v.ext, v.chain, B.work};
-    const Choice vx = pick_variant(nx, ny), vy = pick_variant(ny, nx);
+    const Choice vx = pick_variant(nx, ny, true), vy = pick_variant(ny, nx, true);
     TF_AHIP(hipMemsetAsync(B.mu, 0, N * sizeof(double), s));
     int it;
     bool conv = false;
@@ -894,7 +903,7 @@ tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *r
     if (!ok) st = afail(TF_ENOMEM, "scratch allocation failed");
     if (st == TF_OK) {
         Choice c;
-        if (variant < 0) c = pick_variant(n, nlines);
+        if (variant < 0) c = pick_variant(n, nlines, transposed != 0);
         else c.variant = variant;
         st = sb_solve(c, transposed != 0, 0, nlines, n, bands, rhs, x, nullptr, S, s);
         if (st == TF_OK && hipStreamSynchronize(s) != hipSuccess) st = afail(TF_EDEVICE, "synchronize failed");
@@ -906,7 +915,7 @@ tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *r
     return st;
 }
 
-tf_status tf_autotune(int length, int batch, const char *cache_path)
+tf_status tf_autotune(int length, int batch, int transposed, const char *cache_path)
 {
     if (length < 2 || batch < 1) return afail(TF_EINVAL, "need length >= 2 and batch >= 1");
     const size_t N = (size_t)length * batch;
@@ -946,7 +955,7 @@ tf_status tf_autotune(int length, int batch, const char *cache_path)
             std::vector<float> t;
             for (int r = 0; r < 6 && st == TF_OK; ++r) {
                 (void)hipEventRecord(a, s);
-                st = sb_solve(cands[v], false, 0, batch, length, bands, rhs, x, nullptr, S, s);
+                st = sb_solve(cands[v], transposed != 0, 0, batch, length, bands, rhs, x, nullptr, S, s);
                 (void)hipEventRecord(b, s);
                 (void)hipEventSynchronize(b);
                 float e = 0.0f;
@@ -974,15 +983,15 @@ tf_status tf_autotune(int length, int batch, const char *cache_path)
     {
         TuneTable &t = tune_table();
         std::lock_guard<std::mutex> lk(t.mu);
-        t.best[{length, batch}] = cands[best];
+        t.best[{length, batch, transposed != 0}] = cands[best];
     }
     if (cache_path != nullptr && cache_path[0] != '\0') {
-        // one JSON object per line: {"arch", "length", "batch", "variant", "block", "ms": {...}}
+        // one JSON object per line: {"arch", "length", "batch", "transposed", "variant", "block", "ms": {...}}
         std::ofstream f(cache_path, std::ios::app);
         if (!f) return afail(TF_EINVAL, std::string("cannot write ") + cache_path);
         std::ostringstream o;
         o << "{\"arch\": \"" << arch_name() << "\", \"length\": " << length << ", \"batch\": " << batch
-          << ", \"variant\": \"" << kVariantNames[cands[best].variant] << "\", \"block\": " << cands[best].block
+          << ", \"transposed\": " << (transposed != 0 ? 1 : 0) << ", \"variant\": \"" << kVariantNames[cands[best].variant] << "\", \"block\": " << cands[best].block
           << ", \"ms\": {";
         char buf[64];
         for (size_t v = 0; v < cands.size(); ++v) {
@@ -1021,16 +1030,20 @@ tf_status tf_autotune_load(const char *cache_path)
         };
         if (field("arch") != arch) continue;
         const std::string L = field("length"), Bt = field("batch"), V = field("variant"), Bs = field("block");
+        const std::string Tr = field("transposed");
         if (L.empty() || Bt.empty()) continue;
         Choice c;
         c.variant = V == "thomas" ? V_THOMAS : (V == "pcr" ? V_PCR : V_PARTITIONED);
         c.block = Bs.empty() ? 64 : std::stoi(Bs);
-        t.best[{std::stoi(L), std::stoi(Bt)}] = c;
+        t.best[{std::stoi(L), std::stoi(Bt), Tr.empty() ? 0 : (std::stoi(Tr) != 0)}] = c;
         ++loaded;
     }
     return loaded > 0 ? TF_OK : afail(TF_EINVAL, "no entries for this GPU architecture in the cache");
 }
 
-int tf_autotune_choice(int length, int batch) { return pick_variant(length, batch).variant; }
+int tf_autotune_choice(int length, int batch, int transposed)
+{
+    return pick_variant(length, batch, transposed != 0).variant;
+}
 
 } // extern "C"

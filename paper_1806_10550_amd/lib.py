@@ -84,9 +84,9 @@ def lib():
         L.tf_adjoint_step.argtypes = [P, P, P, D, P, DP, D, C.c_int, IP]
         L.tf_jacobian_apply_t.argtypes = [P, P, P, P]
         L.tf_penta_solve.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, C.c_int, P]
-        L.tf_autotune.argtypes = [C.c_int, C.c_int, C.c_char_p]
+        L.tf_autotune.argtypes = [C.c_int, C.c_int, C.c_int, C.c_char_p]
         L.tf_autotune_load.argtypes = [C.c_char_p]
-        L.tf_autotune_choice.argtypes = [C.c_int, C.c_int]
+        L.tf_autotune_choice.argtypes = [C.c_int, C.c_int, C.c_int]
         L.tf_autotune_choice.restype = C.c_int
         _lib = L
     return _lib
@@ -318,14 +318,32 @@ def penta_solve(bands, rhs, x, transposed=False, variant="auto", stream=None):
     return x
 
 
-def autotune(length: int, batch: int, cache_path: str | None = None) -> str:
-    _check(lib().tf_autotune(int(length), int(batch), cache_path.encode() if cache_path else None))
-    return VARIANT_NAMES[lib().tf_autotune_choice(int(length), int(batch))]
+def autotune(length: int, batch: int, cache_path: str | None = None, transposed: bool = False) -> str:
+    _check(lib().tf_autotune(int(length), int(batch), int(bool(transposed)),
+                             cache_path.encode() if cache_path else None))
+    return VARIANT_NAMES[lib().tf_autotune_choice(int(length), int(batch), int(bool(transposed)))]
 
 
 def autotune_load(cache_path: str) -> None:
     _check(lib().tf_autotune_load(cache_path.encode()))
 
 
-def autotune_choice(length: int, batch: int) -> str:
-    return VARIANT_NAMES[lib().tf_autotune_choice(int(length), int(batch))]
+_shipped_loaded = False
+
+
+def load_shipped_tuning() -> bool:
+    """Load the solver tuning files shipped beside this module (autotune_<arch>.jsonl,
+    written by paper_1806_10550_amd.tune) once per process; entries of other GPU
+    architectures are ignored. Returns True if entries for this GPU were loaded."""
+    global _shipped_loaded
+    if _shipped_loaded:
+        return True
+    import glob
+    for f in sorted(glob.glob(os.path.join(HERE, "autotune_*.jsonl"))):
+        if lib().tf_autotune_load(f.encode()) == TF_OK:
+            _shipped_loaded = True
+    return _shipped_loaded
+
+
+def autotune_choice(length: int, batch: int, transposed: bool = False) -> str:
+    return VARIANT_NAMES[lib().tf_autotune_choice(int(length), int(batch), int(bool(transposed)))]

@@ -170,10 +170,11 @@ def test_autotune_cache_roundtrip(tmp_path):
         assert rec["block"] == int(best.split("/")[1])
     autotune_load(path)
     assert autotune_choice(512, 512) == choice
-    # long lines: no cyclic reduction candidate
-    autotune(4096, 8, path)
+    # long lines: no cyclic reduction candidate; transposed solves are tuned separately
+    ct = autotune(4096, 8, path, transposed=True)
     rec = json.loads(open(path).read().strip().splitlines()[-1])
-    assert "pcr" not in rec["ms"] and rec["length"] == 4096
+    assert "pcr" not in rec["ms"] and rec["length"] == 4096 and rec["transposed"] == 1
+    assert autotune_choice(4096, 8, transposed=True) == ct
 
 
 def test_pcr_rejects_long_lines():
