@@ -475,8 +475,10 @@ __global__ void __launch_bounds__(256) k_jdt_xi(int nx, int ny, double ids, doub
 // out = a lam + b mu + g (local + L(xi))
 __global__ void __launch_bounds__(256) k_jdt_out(int nx, int ny, double ids2, const double *xi, const double *loc,
                                                  const double *lam, const double *mu, double a, double b, double g,
-                                                 double *out)
+                                                 double *out, unsigned long long *clr)
 {
+    // clr (nullable): two reduction words zeroed for a later kernel of the stream
+    if (clr != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) clr[threadIdx.x] = 0ull;
     const int i = blockIdx.x * 64 + (threadIdx.x & 63), j = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (i >= nx || j >= ny) return;
     const size_t o = (size_t)j * nx + i;
@@ -716,14 +718,14 @@ tf_status get_adj(const tf_grid *g, int nx, int ny, AdjBuffers **out)
 }
 
 tf_status jdt(const tf_detail::GridView &v, const double *u, const double *mu, const double *lam, double a, double b,
-              double gmul, double *out, AdjBuffers &B)
+              double gmul, double *out, AdjBuffers &B, unsigned long long *clr = nullptr)
 {
     const double ids = 1.0 / v.ds, ids2 = ids * ids;
     const dim3 grid((v.nx + 63) / 64, (v.ny + 3) / 4), blk(256);
     if (v.M.p32) tf::k_jdt_xi<true><<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids, ids2, v.M, u, mu, B.xi, B.loc);
     else tf::k_jdt_xi<false><<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids, ids2, v.M, u, mu, B.xi, B.loc);
     TF_AHIP(hipGetLastError());
-    tf::k_jdt_out<<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids2, B.xi, B.loc, lam, mu, a, b, gmul, out);
+    tf::k_jdt_out<<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids2, B.xi, B.loc, lam, mu, a, b, gmul, out, clr);
     TF_AHIP(hipGetLastError());
     return TF_OK;
 }
@@ -824,13 +826,13 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
     bool conv = false;
     for (it = 1; it <= max_iter; ++it) {
         // r = lambda - (I + c J^T) mu
-        if ((st = jdt(v, h_np1, B.mu, lambda_inout, 1.0, -1.0, -c, B.r, B)) != TF_OK) return st;
+        // (the reduction words of this iteration's y solve are zeroed by the same kernel)
+        if ((st = jdt(v, h_np1, B.mu, lambda_inout, 1.0, -1.0, -c, B.r, B, B.red)) != TF_OK) return st;
         if ((st = transpose(ny, nx, B.r, B.rT, s)) != TF_OK) return st;
         // (I + c J_x)^-T: rows as lines (transposed layout [i][j])
         if ((st = sb_solve(vx, true, 0, ny, nx, B.bx, B.rT, B.yT, nullptr, S, s)) != TF_OK) return st;
         if ((st = transpose(nx, ny, B.yT, B.y, s)) != TF_OK) return st;
         // (I + c J_y)^-T: columns as lines; mu += z with max|z|, max|mu|
-        TF_AHIP(hipMemsetAsync(B.red, 0, 2 * sizeof(unsigned long long), s));
         if ((st = sb_solve(vy, true, 1, nx, ny, B.by, B.y, B.mu, B.red, S, s)) != TF_OK) return st;
         TF_AHIP(hipMemcpyAsync(B.hred, B.red, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         TF_AHIP(hipStreamSynchronize(s));

@@ -39,6 +39,24 @@ def test_jacobian_transpose_matches_oracle(orc, nx, ny):
     assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("nx,ny", [(8, 6), (67, 130)])
+def test_jacobian_transpose_dot_product(orc, nx, ny):
+    """<w, J_D v> (oracle forward Jacobian) = <J_D^T w, v> (GPU transposed apply): ties the
+    GPU gather form to the forward operator, not only to the oracle's own transpose."""
+    u = synth.noise_film(nx, ny, seed=3 * nx + ny, amp=0.2)
+    rng = np.random.default_rng(nx * ny)
+    v, w = rng.standard_normal((ny, nx)), rng.standard_normal((ny, nx))
+    ds = 0.7
+    g = grid(nx, ny, ds)
+    jtw = torch.empty((ny, nx), dtype=torch.float64, device=DEV)
+    g.jacobian_apply_t(gpu(u), gpu(w), jtw)
+    jv = orc.jacobian_apply(orc.Model(), u, v, ds)
+    jt = jtw.cpu().numpy()
+    lhs, rhs = float(np.sum(w * jv)), float(np.sum(jt * v))
+    scale = float(np.sum(np.abs(w * jv)) + np.sum(np.abs(jt * v)))
+    assert abs(lhs - rhs) <= 1e-12 * scale
+
+
 def _bands(n, nl, seed, dominant=True):
     rng = np.random.default_rng(seed)
     b = rng.standard_normal((5, n, nl))
@@ -66,6 +84,23 @@ def test_penta_solve_matches_oracle(orc, n, nl, transposed, variant):
             band = orc.band_transpose(band)
         ref = orc.band_solve(band, rhs[:, l])
         assert np.max(np.abs(got[:, l] - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), l
+
+
+@pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr"])
+def test_transposed_solve_dot_product(variant):
+    """<w, A^-1 r> = <A^-T w, r> with both solves on the GPU (plain and transposed)."""
+    n, nl = 130, 70
+    b = gpu(_bands(n, nl, seed=11))
+    rng = np.random.default_rng(12)
+    r, w = rng.standard_normal((n, nl)), rng.standard_normal((n, nl))
+    x = torch.empty((n, nl), dtype=torch.float64, device=DEV)
+    y = torch.empty_like(x)
+    penta_solve(b, gpu(r), x, transposed=False, variant=variant)
+    penta_solve(b, gpu(w), y, transposed=True, variant=variant)
+    xs, ys = x.cpu().numpy(), y.cpu().numpy()
+    lhs, rhs = np.sum(w * xs, axis=0), np.sum(ys * r, axis=0)
+    scale = np.sum(np.abs(w * xs), axis=0) + np.sum(np.abs(ys * r), axis=0)
+    assert np.all(np.abs(lhs - rhs) <= 1e-12 * scale)
 
 
 @pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr"])
