@@ -4,6 +4,7 @@
   K = 10): the first accepted steps, every cell, dt schedule and rejections.
 * 8192^2 film (L = 256 lambda_m, dt = 0.2): one full Newton iteration, every cell, and
   the reduction record.
+* 16384^2 film: one Newton iteration (largest size exercised).
 * 2048^2 spinodal over many steps on the GPU alone: mass to 1e-12, positivity.
 """
 import numpy as np
@@ -64,6 +65,29 @@ def test_8192_newton_iteration_matches_oracle(orc):
     v = ref - h0
     assert flags == 0
     assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(v))
+    assert e == pytest.approx(e_ref, rel=1e-9)
+    assert r == pytest.approx(r_ref, rel=1e-9)
+
+
+def test_16384_newton_iteration_matches_oracle(orc):
+    """Largest size exercised: 16384^2 (2.1 GB per field), L = 512 lambda_m; one Newton
+    iteration of the bench's launch configuration against the oracle."""
+    n = 16384
+    ds = 512 * synth.lambda_m(10.0) / n
+    h0 = synth.noise_film(n, n, seed=7, amp=0.01)
+    g = Grid(n, n, ds)
+    g.set_model(10.0, 0.1, 3, 2)
+    g.set_scheme(theta=1.0, tol=1e-10)
+    un = torch.from_numpy(h0).to(DEV)
+    out = torch.empty_like(un)
+    e, r, flags = g.newton_iteration(un, un, out, 0.2)
+    got = out.cpu().numpy()
+    del out, un
+    g.close()
+    torch.cuda.empty_cache()
+    ref, e_ref, r_ref = orc.adi_iteration(orc.Model(), h0, h0, ds, 0.2, 1.0)
+    assert flags == 0
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref - h0))
     assert e == pytest.approx(e_ref, rel=1e-9)
     assert r == pytest.approx(r_ref, rel=1e-9)
 
