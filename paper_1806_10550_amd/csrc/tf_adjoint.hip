@@ -737,23 +737,29 @@ tf_status transpose(int rows, int cols, const double *in, double *out, hipStream
     return TF_OK;
 }
 
-tf_status dot(const double *x, const double *a, const double *b, double wa, double wb, size_t n, AdjBuffers &B,
-              hipStream_t s, double *res)
+// Enqueue x . (wa a + wb b) as per-block compensated partials copied to pinned host
+// memory; dot_finish combines them after the caller has synchronised the stream.
+tf_status dot_enqueue(const double *x, const double *a, const double *b, double wa, double wb, size_t n,
+                      AdjBuffers &B, hipStream_t s, size_t *nblocks)
 {
     size_t nb = (n + 255) / 256;
     if (nb > 4096) nb = 4096;
     tf::k_dot<<<dim3((unsigned)nb), dim3(256), 0, s>>>(x, a, b, wa, wb, n, B.part);
     TF_AHIP(hipGetLastError());
     TF_AHIP(hipMemcpyAsync(B.hpart, B.part, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
-    TF_AHIP(hipStreamSynchronize(s));
+    *nblocks = nb;
+    return TF_OK;
+}
+
+double dot_finish(const AdjBuffers &B, size_t nb)
+{
     double sum = 0.0, c = 0.0;
     for (size_t k = 0; k < nb; ++k) {
         const double p = B.hpart[2 * k], t = sum + p;
         c += (std::fabs(sum) >= std::fabs(p) ? (sum - t) + p : (p - t) + sum) + B.hpart[2 * k + 1];
         sum = t;
     }
-    *res = sum + c;
-    return TF_OK;
+    return sum + c;
 }
 
 double bits_to_double(unsigned long long x)
@@ -821,7 +827,9 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
     }
     Scratch S{v.rel, v.ext, v.chain, B.work};
     const Choice vx = pick_variant(nx, ny, true), vy = pick_variant(ny, nx, true);
-    TF_AHIP(hipMemsetAsync(B.mu, 0, N * sizeof(double), s));
+    // initial guess mu = lambda^{n+1} (the solution for dt -> 0; only the number of
+    // iterations depends on it)
+    TF_AHIP(hipMemcpyAsync(B.mu, lambda_inout, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     int it;
     bool conv = false;
     for (it = 1; it <= max_iter; ++it) {
@@ -845,6 +853,7 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
     }
     if (iters_out) *iters_out = conv ? it : max_iter;
     if (!conv) return afail(TF_ENOCONV, "adjoint Richardson iteration did not converge");
+    size_t dot_blocks = 0;
     // kappa gradient: dL/dkappa -= dt mu . [theta dD/dk(u^{n+1}) + (1 - theta) dD/dk(u^n)]
     if (dL_dkappa_accum != nullptr) {
         tf::Model Mk = v.M; // f1 with kappa = 1, f0 dropped
@@ -860,10 +869,9 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
         }
         TF_AHIP(tf::launch_flux_divergence_f1(nx, ny, ids, ids2, Mk, h_np1, B.dk1, s));
         if (v.theta < 1.0) TF_AHIP(tf::launch_flux_divergence_f1(nx, ny, ids, ids2, Mk, h_n, B.dk0, s));
-        double d;
-        if ((st = dot(B.mu, B.dk1, v.theta < 1.0 ? B.dk0 : nullptr, v.theta, 1.0 - v.theta, N, B, s, &d)) != TF_OK)
+        if ((st = dot_enqueue(B.mu, B.dk1, v.theta < 1.0 ? B.dk0 : nullptr, v.theta, 1.0 - v.theta, N, B, s,
+                              &dot_blocks)) != TF_OK)
             return st;
-        *dL_dkappa_accum -= dt * d;
     }
     // lambda^n = mu - (1 - theta) dt J_D(u^n)^T mu
     if (v.theta < 1.0) {
@@ -872,6 +880,7 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
         TF_AHIP(hipMemcpyAsync(lambda_inout, B.mu, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     TF_AHIP(hipStreamSynchronize(s));
+    if (dot_blocks > 0) *dL_dkappa_accum -= dt * dot_finish(B, dot_blocks);
     return TF_OK;
 }
 
