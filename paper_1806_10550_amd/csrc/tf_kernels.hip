@@ -413,7 +413,8 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
         return;
     } else {
         __syncthreads(); // relation records consumed: sB becomes the output staging tile
-        double emax = 0.0;
+        // back-substitution stages v; u_{k+1} = u_k + v, the update ratio and the flags
+        // are formed in the row-wise store loop (u_k from the LDS u tile)
         if (len > 0) {
 #pragma unroll
             for (int k = SUB - 1; k >= 0; --k) {
@@ -421,32 +422,30 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
                     const double v = fz[k] + fph[k] * wl1 + fps[k] * wl2 - fa[k] * xr1 - fb[k] * xr2;
                     xr2 = xr1;
                     xr1 = v;
-                    const double uk = uat<DIR>(sU, lane, ps + k);
-                    const double un = uk + v;
-                    if (owned) {
-                        emax = fmax(emax, fabs(v) * rcp(fabs(uk)));
-                        if (!(un > 0.0)) flags |= (un != un || v != v) ? FLAG_NAN : FLAG_NONPOS;
-                    }
-                    sB[lane * WPITCH + ps + k] = un;
+                    sB[lane * WPITCH + ps + k] = v;
                 }
+            }
+        }
+        __syncthreads();
+        double emax = 0.0;
+#pragma unroll
+        for (int r = 0; r < TILE / NSUB; ++r) {
+            const int ly = wave + NSUB * r;
+            if (ly < nlt && lane < npos) {
+                const double v = sB[ly * WPITCH + lane];
+                const double uk = uat<DIR>(sU, ly, lane);
+                const double un = uk + v;
+                emax = fmax(emax, fabs(v) * rcp(fabs(uk)));
+                if (!(un > 0.0)) flags |= (un != un || v != v) ? FLAG_NAN : FLAG_NONPOS;
+                (p.out + (size_t)(y0 + ly) * nx + x0)[(unsigned)lane] = un;
             }
         }
         const double wm = wave_max(emax);
         const unsigned wf = wave_or(flags);
-        if (lane == 0) { sRed[wave] = wm; sFlag[wave] = wf; }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < TILE / NSUB; ++r) {
-            const int ly = wave + NSUB * r;
-            if (ly < nlt && lane < npos) (p.out + (size_t)(y0 + ly) * nx + x0)[(unsigned)lane] = sB[ly * WPITCH + lane];
-        }
-        if (tid == 0 && p.res != nullptr) {
-            double m = 0.0;
-            unsigned f = 0;
-            for (int w = 0; w < NSUB; ++w) { m = fmax(m, sRed[w]); f |= sFlag[w]; }
-            unsigned long long *rs = p.res + (size_t)(blockIdx.x % p.res_spread) * RES_WORDS;
-            atomicMax(&rs[RES_EMAX], (unsigned long long)__double_as_longlong(m));
-            if (f) atomicOr(&rs[RES_FLAGS], (unsigned long long)f);
+        if (lane == 0 && p.res != nullptr) {
+            unsigned long long *rs = p.res + (size_t)((blockIdx.x * NSUB + wave) % p.res_spread) * RES_WORDS;
+            atomicMax(&rs[RES_EMAX], (unsigned long long)__double_as_longlong(wm));
+            if (wf) atomicOr(&rs[RES_FLAGS], (unsigned long long)wf);
         }
     }
 }
