@@ -27,7 +27,7 @@ namespace tf {
 #define K1Y_WAVES_PER_EU 4
 #endif
 #ifndef K1X_WAVES_PER_EU
-#define K1X_WAVES_PER_EU 2
+#define K1X_WAVES_PER_EU 3
 #endif
 #ifndef K1_UNROLL
 #define K1_UNROLL 1
@@ -36,7 +36,7 @@ namespace tf {
 #define K1Y_FAST_UNROLL 2
 #endif
 #ifndef K1X_FAST_UNROLL
-#define K1X_FAST_UNROLL 16
+#define K1X_FAST_UNROLL 4
 #endif
 
 // ------------------------------------------------------------------------------------
@@ -120,6 +120,8 @@ __device__ __forceinline__ void sweep(const double *sU, const double *sB, const 
                                       double &rmax, unsigned &flags)
 {
     const double ka = p.ka;
+    // x relations pass: w read straight from global memory (each lane walks its row)
+    constexpr bool WG = DIR == 1 && !SOLVE;
     {
         const CellS cm = cell_s<DIR, P32>(sU, p, lane, ps - 1);
         CellS c0 = cell_s<DIR, P32>(sU, p, lane, ps);
@@ -158,7 +160,7 @@ __device__ __forceinline__ void sweep(const double *sU, const double *sB, const 
                         if (G != G) flags |= FLAG_NAN;
                     }
                 } else {
-                    rhs = sB[lane * WPITCH + lp];
+                    rhs = WG ? bcol[k] : sB[lane * WPITCH + lp];
                 }
                 // bands of I + c J along the line from the two face records
                 double a = fm.kA;
@@ -277,13 +279,14 @@ __device__ __forceinline__ void stage_tile(const PassParams &p, double *sU, doub
 template <int DIR, bool SOLVE, bool P32>
 __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
 {
-    // LDS: the u tile, then the tile of the second input (b^n, w) which the solve passes
-    // later reuse for the relation exchange and (x solve) the output tile. The relations
-    // passes exchange in the u tile once the sweeps are done. The y relations pass reads
-    // b^n straight from global memory (lanes cover consecutive x), which keeps its LDS
-    // footprint at one tile, so that four workgroups fit on a CU.
+    // LDS: the u tile, then (solve passes) the tile of the second input (b^n, w) which
+    // is later reused for the relation exchange and (x solve) the output tile. The
+    // relations passes exchange in the u tile once the sweeps are done; they read their
+    // right-hand side straight from global memory (y: lanes cover consecutive x; x: each
+    // lane walks its row), which keeps their LDS footprint at one tile, so that three or
+    // four workgroups fit on a CU.
     constexpr int NU = TW * UPITCH, NX = NSUB * NREL * 64, NW = TILE * WPITCH;
-    constexpr bool STAGE_B = DIR == 1 || SOLVE;
+    constexpr bool STAGE_B = SOLVE;
     constexpr int NLDS = SOLVE ? NU + NX : (STAGE_B ? NU + NW : NU);
     static_assert(NX >= NW && NU >= (NSUB - 1) * NREL * 64, "LDS regions too small");
     __shared__ double lds[NLDS];
@@ -330,7 +333,8 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
     const bool fast = npos == TILE && pbase >= 2 && pbase + TILE <= Np - 2
                       && (DIR == 1 || (x0 > 0 && x0 + LT0 < nx && nlt == LT0));
     // per-lane column of b^n for the y relations pass (read from global memory)
-    const double *bcol = p.in2 + crefl(bxo + lane, nx);
+    const double *bcol = DIR == 0 ? p.in2 + crefl(bxo + lane, nx)
+                                  : p.in2 + (size_t)min(y0 + lane, ny - 1) * nx + (x0 + ps);
     if (len > 0) {
         if (fast)
             sweep<DIR, SOLVE, P32, true>(sU, sB, bcol, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph,
