@@ -1,0 +1,78 @@
+"""Host-side behaviour of the C ABI that needs no GPU: argument validation returns
+TF_EINVAL (with a message) before any device call, and the solver choice falls back to
+its documented heuristic when nothing has been tuned."""
+import ctypes as C
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1806_10550_amd", "libthinfilm.so")
+TF_EINVAL = 1
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libthinfilm.so not built")
+
+
+@pytest.fixture(scope="module")
+def L():
+    lib = C.CDLL(LIB)
+    lib.tf_last_error.restype = C.c_char_p
+    lib.tf_create.argtypes = [C.c_int, C.c_int, C.c_double, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.tf_ensemble_create.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                       C.c_double, C.c_double, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.tf_penta_solve.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                   C.c_void_p]
+    lib.tf_autotune.argtypes = [C.c_int, C.c_int, C.c_int, C.c_char_p]
+    lib.tf_autotune_load.argtypes = [C.c_char_p]
+    lib.tf_autotune_choice.argtypes = [C.c_int, C.c_int, C.c_int]
+    lib.tf_set_model.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double]
+    lib.tf_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.tf_adjoint_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                    C.c_double, C.c_int, C.c_void_p]
+    return lib
+
+
+def test_create_rejects_bad_geometry(L):
+    out = C.c_void_p(1)
+    assert L.tf_create(3, 8, 0.5, None, C.byref(out)) == TF_EINVAL
+    assert out.value is None
+    assert b"nx and ny" in L.tf_last_error()
+    assert L.tf_create(8, 8, 0.0, None, C.byref(out)) == TF_EINVAL
+    assert L.tf_create(8, 8, float("inf"), None, C.byref(out)) == TF_EINVAL
+    assert L.tf_create(8, 8, 0.5, None, None) == TF_EINVAL
+
+
+def test_ensemble_create_rejects_bad_model(L):
+    out = C.c_void_p(1)
+    nx = (C.c_int * 1)(64)
+    ds = (C.c_double * 1)(0.5)
+    assert L.tf_ensemble_create(0, nx, nx, ds, ds, 0.1, 3.0, 2.0, None, C.byref(out)) == TF_EINVAL
+    assert L.tf_ensemble_create(1, nx, nx, ds, ds, 0.1, 2.5, 2.0, None, C.byref(out)) == TF_EINVAL
+    assert L.tf_ensemble_create(1, nx, nx, ds, ds, 0.1, 2.0, 3.0, None, C.byref(out)) == TF_EINVAL
+    assert L.tf_ensemble_create(1, nx, nx, ds, ds, -0.1, 3.0, 2.0, None, C.byref(out)) == TF_EINVAL
+    assert b"exponents" in L.tf_last_error()
+
+
+def test_null_handles(L):
+    assert L.tf_set_model(None, 10.0, 0.1, 3.0, 2.0) == TF_EINVAL
+    assert L.tf_step(None, None, None) == TF_EINVAL
+    assert L.tf_adjoint_step(None, None, None, 0.1, None, None, 1e-10, 10, None) == TF_EINVAL
+
+
+def test_penta_solve_validates_before_allocating(L):
+    p = C.c_void_p(16)  # never dereferenced: validation fails first
+    assert L.tf_penta_solve(0, 8, p, p, p, 0, 0, None) == TF_EINVAL
+    assert L.tf_penta_solve(4, 1, p, p, p, 0, 0, None) == TF_EINVAL
+    assert L.tf_penta_solve(4, 8, p, p, p, 0, 3, None) == TF_EINVAL
+    assert L.tf_penta_solve(4, 4096, p, p, p, 0, 2, None) == TF_EINVAL
+    assert b"2048" in L.tf_last_error()
+
+
+def test_autotune_arguments_and_default_choice(L, tmp_path):
+    assert L.tf_autotune(1, 16, 0, None) == TF_EINVAL
+    assert L.tf_autotune(128, 0, 1, None) == TF_EINVAL
+    assert L.tf_autotune_load(None) == TF_EINVAL
+    assert L.tf_autotune_load(str(tmp_path / "missing.jsonl").encode()) == TF_EINVAL
+    # nothing tuned in this process: partitioned below 65536 lines, Thomas from there on
+    assert L.tf_autotune_choice(512, 512, 1) == 0
+    assert L.tf_autotune_choice(128, 65536, 0) == 1
