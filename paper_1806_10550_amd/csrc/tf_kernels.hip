@@ -45,6 +45,21 @@ namespace tf {
 // y-sweep tiles own LT0 = 62 columns: lanes 0 and 63 carry the neighbouring columns so
 // that the x faces of the residual come from lane shuffles.
 // ------------------------------------------------------------------------------------
+// Value of the next (lane + 1) / previous (lane - 1) lane of the wave by whole-wave DPP
+// shifts (VALU moves, no LDS permute); the edge lanes get 0 (the sweeps use them only
+// for halo lanes).
+__device__ __forceinline__ double dpp_shift(double v, int ctrl)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = ctrl == 0x130 ? __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, false)
+                                 : __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, false);
+    const int hi = ctrl == 0x130 ? __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, false)
+                                 : __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_next(double v) { return dpp_shift(v, 0x130); } // wave_shl:1
+__device__ __forceinline__ double lane_prev(double v) { return dpp_shift(v, 0x138); } // wave_shr:1
+
 // Per-cell quantities of the sweeps, scaled so that each face record takes few
 // operations (ka = c / (2 ds^2), c = theta dt):
 //   lap = u_E + u_W + u_N + u_S - 4u      (ds^2 times the 5-point Laplacian)
@@ -145,11 +160,11 @@ __device__ __forceinline__ void sweep(const double *sU, const double *sB, const 
                 if (DIR == 0) {
                     // -G(u_k) = -(u_k - b^n + theta dt D(u_k)); the x faces of this cell
                     // use the neighbouring lanes' cell values
-                    const double eu = __shfl_down(c0.u, 1), el = __shfl_down(c0.lap, 1);
-                    const double e0 = __shfl_down(c0.f0, 1), e1 = __shfl_down(c0.f1, 1);
+                    const double eu = lane_next(c0.u), el = lane_next(c0.lap);
+                    const double e0 = lane_next(c0.f0), e1 = lane_next(c0.f1);
                     const double Fe0 = __builtin_fma(c0.f0 + e0, el - c0.lap, (c0.f1 + e1) * (eu - c0.u));
                     const double Fe = (FAST || gl < Nl - 1) ? Fe0 : 0.0;
-                    const double Fwr = __shfl_up(Fe, 1);
+                    const double Fwr = lane_prev(Fe);
                     const double Fw = (FAST || gl > 0) ? Fwr : 0.0;
                     const double D = (Fe - Fw) + (fp.F - fm.F);
                     const double bn = SOLVE ? sB[lp * WPITCH + lane] : bcol[(size_t)gp * p.nx];
