@@ -214,6 +214,7 @@ __device__ __forceinline__ void chain_symbolic(const Rel &first, const double *r
 // Numeric version with the outer values known: returns the boundary values of
 // sub-segment w, lo = B_{w-1} (the outer l for w = 0) and hi = T_{w+1} (outer r for the
 // last sub-segment).
+template <bool SKIP_LAST_B = false>
 __device__ __forceinline__ void chain_numeric(const double *sB, int lane, int Q, int w, double l1, double l2,
                                               double r1, double r2, double &lo1, double &lo2, double &hi1,
                                               double &hi2)
@@ -227,8 +228,20 @@ __device__ __forceinline__ void chain_numeric(const double *sB, int lane, int Q,
 #pragma unroll
     for (int q = 0; q < NSUB; ++q) {
         if (q >= Q) break;
+        // the bottom pair of the last sub-segment is never used (SKIP_LAST_B: not exchanged)
         Rel S;
-        load_rel(sB, q, lane, S);
+        if (!SKIP_LAST_B) {
+            load_rel(sB, q, lane, S);
+        } else {
+            const double *src = sB + (size_t)q * NREL * 64 + lane;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 5; ++j) {
+                    S.T[i][j] = src[(i * 5 + j) * 64];
+                    S.B[i][j] = q < Q - 1 ? src[(10 + i * 5 + j) * 64] : 0.0;
+                }
+        }
         const M2 Tl = {S.T[0][1], S.T[0][2], S.T[1][1], S.T[1][2]};
         const M2 Tr = {S.T[0][3], S.T[0][4], S.T[1][3], S.T[1][4]};
         const M2 Bl = {S.B[0][1], S.B[0][2], S.B[1][1], S.B[1][2]};

@@ -129,7 +129,7 @@ __device__ __forceinline__ FaceS face_s(const CellS &L, const CellS &R, bool int
 // symbolic. FAST: interior tile with 16 positions per wave, no domain boundary inside
 // (no folded ghost columns, no zero-flux faces, no per-lane boundary selects).
 template <int DIR, bool SOLVE, bool P32, bool FAST>
-__device__ __forceinline__ void sweep(const double *sU, const double *sB, const double *bcol, const PassParams &p,
+__device__ __forceinline__ void sweep(const double *sU, double *sB, const double *bcol, const PassParams &p,
                                       int lane, int ps, int len, int pbase, int Np, int gl, int Nl, bool owned, double *fa,
                                       double *fb, double *fz, double *fph, double *fps, Rel &mine,
                                       double &rmax, unsigned &flags)
@@ -206,7 +206,11 @@ __device__ __forceinline__ void sweep(const double *sU, const double *sB, const 
                 sgz += g * z; sgph += g * ph; sgps += g * pss;
                 shz += h * z; shph += h * ph; shps += h * pss;
                 if (SOLVE) {
-                    fa[k] = al; fb[k] = be; fz[k] = z; fph[k] = ph; fps[k] = pss;
+                    fa[k] = al; fb[k] = be; fz[k] = z; fph[k] = ph;
+                    // y solve: the coefficient of l2 is parked in the LDS slot of the b^n value
+                    // just consumed (only this wave reads its positions' slots)
+                    if (DIR == 0) sB[lp * WPITCH + lane] = pss;
+                    else fps[k] = pss;
                 }
                 g2 = g1; g1 = g; h2 = h1; h1 = h;
                 al2 = al1; be2 = be1; al1 = al; be1 = be;
@@ -302,14 +306,17 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
     // four workgroups fit on a CU.
     constexpr int NU = TW * UPITCH, NX = NSUB * NREL * 64, NW = TILE * WPITCH;
     constexpr bool STAGE_B = SOLVE;
-    constexpr int NLDS = SOLVE ? NU + NX : (STAGE_B ? NU + NW : NU);
-    static_assert(NX >= NW && NU >= (NSUB - 1) * NREL * 64, "LDS regions too small");
+    // y solve: the b^n tile keeps the parked factors, so its exchange goes to the u tile
+    // (without the never-used bottom pair of the last sub-segment)
+    constexpr bool XU = DIR == 0 && SOLVE;
+    constexpr int NLDS = XU ? NU + NW : (SOLVE ? NU + NX : (STAGE_B ? NU + NW : NU));
+    static_assert(NX >= NW && NU >= (NSUB - 1) * NREL * 64 + 10 * 64, "LDS regions too small");
     __shared__ double lds[NLDS];
     __shared__ double sRed[NSUB];
     __shared__ unsigned sFlag[NSUB];
     double *const sU = lds;
     double *const sB = lds + NU;                 // second input, then exchange / output
-    double *const xch = SOLVE ? sB : lds;        // relation exchange
+    double *const xch = (SOLVE && !XU) ? sB : lds; // relation exchange
 
     const int nx = p.nx, ny = p.ny;
     int x0, x1, y0, y1;
@@ -383,7 +390,7 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
 #pragma unroll
             for (int j = 0; j < 5; ++j) {
                 dst[(i * 5 + j) * 64] = mine.T[i][j];
-                dst[(10 + i * 5 + j) * 64] = mine.B[i][j];
+                if (!XU || wave < NSUB - 1) dst[(10 + i * 5 + j) * 64] = mine.B[i][j];
             }
     }
     __syncthreads();
@@ -414,7 +421,7 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
 
     // ---- SOLVE: boundary values of this wave's sub-segment, then back-substitution
     double wl1 = 0.0, wl2 = 0.0, xr1 = 0.0, xr2 = 0.0;
-    if (len > 0) chain_numeric(xch, lane, nsub, wave, l1, l2, r1, r2, wl1, wl2, xr1, xr2);
+    if (len > 0) chain_numeric<XU>(xch, lane, nsub, wave, l1, l2, r1, r2, wl1, wl2, xr1, xr2);
 
     if (DIR == 0) {
         // w goes straight from registers to memory: lanes cover consecutive x
@@ -422,7 +429,7 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
 #pragma unroll
             for (int k = SUB - 1; k >= 0; --k) {
                 if (k < len) {
-                    const double x = fz[k] + fph[k] * wl1 + fps[k] * wl2 - fa[k] * xr1 - fb[k] * xr2;
+                    const double x = fz[k] + fph[k] * wl1 + sB[(ps + k) * WPITCH + lane] * wl2 - fa[k] * xr1 - fb[k] * xr2;
                     if (owned) (p.out + (size_t)(pbase + ps + k) * nx)[(unsigned)gl] = x;
                     xr2 = xr1;
                     xr1 = x;
