@@ -173,6 +173,14 @@ def bench_adjoint(args):
     fwd_iters = sum(x["total_iters"] for x in log)
     p0 = torch.zeros_like(base, requires_grad=True)
     kap = torch.tensor(cfg.kappa, dtype=torch.float64, device=dev, requires_grad=True)
+    # warm-up: a short rollout through forward and backward (first kernel loads, the
+    # adjoint scratch of a grid, the solver tuning table), as the forward was warmed up
+    # by the target run
+    w = rollout(p0, kap, base, cfg.extra["checkpoint_every"], dt, cfg.ds,
+                checkpoint_every=cfg.extra["checkpoint_every"], tol=cfg.tol, adj_tol=cfg.tol)
+    (0.5 * torch.sum((w - tgt) ** 2)).backward()
+    p0.grad = None
+    kap.grad = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     # the adjoint iteration stops at the forward Newton tolerance: the states it

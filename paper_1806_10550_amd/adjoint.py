@@ -14,6 +14,20 @@ import torch
 from .lib import Grid, load_shipped_tuning
 
 
+# Grids (and with them their device scratch and adjoint buffers) are reused across
+# rollouts of the same geometry; every forward and backward pass sets the model and the
+# scheme it needs before using one.
+_grids = {}
+
+
+def _grid(nx, ny, ds):
+    key = (nx, ny, float(ds))
+    g = _grids.get(key)
+    if g is None:
+        g = _grids[key] = Grid(nx, ny, ds)
+    return g
+
+
 class Rollout(torch.autograd.Function):
     # totals of the last backward pass: adjoint steps and Richardson iterations
     stats = {"adjoint_steps": 0, "richardson_iters": 0}
@@ -22,8 +36,9 @@ class Rollout(torch.autograd.Function):
     def forward(ctx, p0, kappa, h_base, nsteps: int, dt: float, ds: float, checkpoint_every: int = 20,
                 tol: float = 1e-10, adj_tol: float = 1e-13, b: float = 0.1, n: int = 3, m: int = 2):
         ny, nx = h_base.shape
-        g = Grid(nx, ny, ds)
-        g.set_model(float(kappa.detach().item()), b, n, m)
+        g = _grid(nx, ny, ds)
+        model = (float(kappa.detach().item()), b, n, m)
+        g.set_model(*model)
         g.set_scheme(theta=1.0, tol=tol, max_newton=5000)
         h = (h_base + p0).detach().contiguous().clone()
         g.bind(h)
@@ -34,14 +49,16 @@ class Rollout(torch.autograd.Function):
                 ckpts.append(h.clone())
         ctx.grid = g
         ctx.ckpts = ckpts
-        ctx.cfg = (nsteps, dt, checkpoint_every, adj_tol)
+        ctx.cfg = (nsteps, dt, checkpoint_every, adj_tol, model, tol)
         ctx.kappa_shape = kappa.shape
         return h.clone()
 
     @staticmethod
     def backward(ctx, grad_h):
         g = ctx.grid
-        nsteps, dt, K, adj_tol = ctx.cfg
+        nsteps, dt, K, adj_tol, model, tol = ctx.cfg
+        g.set_model(*model)
+        g.set_scheme(theta=1.0, tol=tol, max_newton=5000)
         load_shipped_tuning()  # solver variants tuned for this GPU, if shipped
         steps = iters = 0
         lam = grad_h.detach().contiguous().clone()
