@@ -19,12 +19,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 OK, EINVAL, ENOMEM, ENOCONV, ENONPOS, ESINGULAR = 0, 1, 2, 4, 5, 7
-POWERLAW, LINEAR = 0, 1
+POWERLAW, LINEAR, NLC, POLYMER = 0, 1, 2, 3
 
 
 class _Model(C.Structure):
     _fields_ = [("kind", C.c_int), ("kappa", C.c_double), ("b", C.c_double), ("n", C.c_double),
-                ("m", C.c_double), ("c0", C.c_double), ("c1", C.c_double)]
+                ("m", C.c_double), ("c0", C.c_double), ("c1", C.c_double), ("cap", C.c_double),
+                ("K", C.c_double), ("N", C.c_double), ("beta", C.c_double), ("w", C.c_double),
+                ("Cst", C.c_double), ("Aox", C.c_double), ("Asi", C.c_double), ("d", C.c_double)]
 
 
 class _Scheme(C.Structure):
@@ -51,13 +53,35 @@ class Model:
     kind: int = POWERLAW
     c0: float = 0.0
     c1: float = 0.0
+    cap: float = 1.0
+    K: float = 0.0
+    N: float = 0.0
+    beta: float = 0.0
+    w: float = 0.0
+    Cst: float = 0.0
+    Aox: float = 0.0
+    Asi: float = 0.0
+    d: float = 0.0
 
     @staticmethod
     def linear(c0: float, c1: float) -> "Model":
         return Model(kind=LINEAR, c0=c0, c1=c1)
 
+    @staticmethod
+    def nlc(cap=0.0857, K=36.0, N=1.67, beta=1.0, w=0.05, b=0.01) -> "Model":
+        """NLC model: f0 = C h^3, f1 = h^3 Pi'(h), Pi of eqs. DisjPressNLC, mh_model; defaults
+        are the parameters of eq. NLC_paras."""
+        return Model(kind=NLC, cap=cap, K=K, N=N, beta=beta, w=w, b=b)
+
+    @staticmethod
+    def polymer(cap=0.00581, Cst=1.181, Aox=41.25, Asi=-243.75, d=191.0) -> "Model":
+        """Polymer model: f0 = C h^3, f1 = h^3 Pi'(h), Pi = -psi' of eq. DisjPressPolymer;
+        defaults are the parameters of eq. Polymer_scales."""
+        return Model(kind=POLYMER, cap=cap, Cst=Cst, Aox=Aox, Asi=Asi, d=d)
+
     def _c(self) -> _Model:
-        return _Model(self.kind, self.kappa, self.b, self.n, self.m, self.c0, self.c1)
+        return _Model(self.kind, self.kappa, self.b, self.n, self.m, self.c0, self.c1, self.cap, self.K,
+                      self.N, self.beta, self.w, self.Cst, self.Aox, self.Asi, self.d)
 
 
 @dataclass
@@ -94,6 +118,7 @@ def lib():
         L.or_set_threads.argtypes = [C.c_int]
         L.or_get_threads.restype = C.c_int
         L.or_coeffs.argtypes = [MP, C.c_double] + [C.POINTER(C.c_double)] * 4
+        L.or_disjoining.argtypes = [MP, C.c_double] + [C.POINTER(C.c_double)] * 3
         L.or_flux_divergence.argtypes = [MP, C.c_int, C.c_int, C.c_double, _DP, _DP]
         L.or_flux_divergence_dkappa.argtypes = [MP, C.c_int, C.c_int, C.c_double, _DP, _DP]
         L.or_residual.argtypes = [MP, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
@@ -127,6 +152,14 @@ def set_threads(n: int) -> None:
 
 def get_threads() -> int:
     return int(lib().or_get_threads())
+
+
+def disjoining(model: Model, h: float):
+    """(Pi, Pi', Pi'') at one thickness h for the NLC and polymer models."""
+    out = [C.c_double() for _ in range(3)]
+    m = model._c()
+    lib().or_disjoining(C.byref(m), float(h), *[C.byref(o) for o in out])
+    return tuple(o.value for o in out)
 
 
 def coeffs(model: Model, h: float):

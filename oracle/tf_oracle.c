@@ -21,6 +21,8 @@
  *                                           elimination with partial pivoting)
  *   model f0 = h^3, f1 = kappa h^3 f'(h),   eq. GeneralDisPreForm with the power-law part
  *   f = (b/h)^n - (b/h)^m                   of eq. DisjPressNLC
+ *   NLC model f0 = C h^3, f1 = h^3 Pi'(h)   eqs. GeneralDisPreForm, DisjPressNLC, mh_model
+ *   polymer model, same f0, f1              eqs. GeneralDisPreForm, DisjPressPolymer
  *   linear test model f0 = c0, f1 = c1      Sec. "Thin Film Models"
  *
  * Readings of points the paper leaves open are listed where they are used.
@@ -30,6 +32,9 @@
  * except exact maxima).
  */
 #include <math.h>
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -38,12 +43,15 @@
 
 /* status codes (same numeric meaning as the GPU library's, defined here on purpose) */
 enum { OR_OK = 0, OR_EINVAL = 1, OR_ENOMEM = 2, OR_ENOCONV = 4, OR_ENONPOS = 5, OR_ESINGULAR = 7 };
-enum { OR_POWERLAW = 0, OR_LINEAR = 1 };
+enum { OR_POWERLAW = 0, OR_LINEAR = 1, OR_NLC = 2, OR_POLYMER = 3 };
 
 typedef struct {
-    int kind;        /* OR_POWERLAW or OR_LINEAR */
+    int kind;        /* OR_POWERLAW, OR_LINEAR, OR_NLC or OR_POLYMER */
     double kappa, b, n, m; /* power law: f(h) = (b/h)^n - (b/h)^m, f1 = kappa h^3 f'(h) */
     double c0, c1;   /* linear test model */
+    double cap;      /* NLC / polymer: inverse capillary number C in f0 = C h^3 */
+    double K, N, beta, w; /* NLC: Pi = K[(b/h)^3 - (b/h)^2] + N/2 (m(h)/h)^2 (b as above) */
+    double Cst, Aox, Asi, d; /* polymer: psi = Cst/h^8 - Aox/(12 pi h^2) + (Aox - Asi)/(12 pi (h+d)^2) */
 } or_model;
 
 typedef struct {
@@ -81,10 +89,52 @@ int or_get_threads(void)
  * f0 = h^3, f1 = kappa h^3 f'(h), with f(h) = (b/h)^n - (b/h)^m, written out from
  * the definitions; f0', f1' are their h-derivatives.
  * ------------------------------------------------------------------------- */
+/* Disjoining pressure Pi(h) and its first two derivatives for the NLC model (eqs.
+ * DisjPressNLC, mh_model) and the polymer model (eq. DisjPressPolymer, Pi = -psi').
+ * Written out from the definitions:
+ *   NLC:  Pi = K (b^3 h^-3 - b^2 h^-2) + N/2 q^2,  q = m(h)/h = g(h) r(h),
+ *         g = (1 + tanh z)/2, z = (h - 2b)/w,  r = h / (h^2 + beta^2);
+ *   polymer: Pi = 8 Cst h^-9 - 2a h^-3 + 2c (h+d)^-3,  a = Aox/(12 pi), c = (Aox-Asi)/(12 pi). */
+void or_disjoining(const or_model *M, double h, double *Pi, double *Pip, double *Pipp)
+{
+    if (M->kind == OR_NLC) {
+        const double b = M->b, K = M->K, N = M->N, be2 = M->beta * M->beta, w = M->w;
+        const double z = (h - 2.0 * b) / w, th = tanh(z), sech2 = 1.0 - th * th;
+        const double g = 0.5 * (1.0 + th);
+        const double gp = 0.5 * sech2 / w;
+        const double gpp = -sech2 * th / (w * w);
+        const double den = h * h + be2;
+        const double r = h / den;
+        const double rp = (be2 - h * h) / (den * den);
+        const double rpp = 2.0 * h * (h * h - 3.0 * be2) / (den * den * den);
+        const double q = g * r, qp = gp * r + g * rp, qpp = gpp * r + 2.0 * gp * rp + g * rpp;
+        const double b2 = b * b, b3 = b2 * b;
+        *Pi = K * (b3 / (h * h * h) - b2 / (h * h)) + 0.5 * N * q * q;
+        *Pip = K * (-3.0 * b3 / pow(h, 4.0) + 2.0 * b2 / (h * h * h)) + N * q * qp;
+        *Pipp = K * (12.0 * b3 / pow(h, 5.0) - 6.0 * b2 / pow(h, 4.0)) + N * (qp * qp + q * qpp);
+    } else {
+        const double a = M->Aox / (12.0 * M_PI), c = (M->Aox - M->Asi) / (12.0 * M_PI), hd = h + M->d;
+        *Pi = 8.0 * M->Cst / pow(h, 9.0) - 2.0 * a / pow(h, 3.0) + 2.0 * c / pow(hd, 3.0);
+        *Pip = -72.0 * M->Cst / pow(h, 10.0) + 6.0 * a / pow(h, 4.0) - 6.0 * c / pow(hd, 4.0);
+        *Pipp = 720.0 * M->Cst / pow(h, 11.0) - 24.0 * a / pow(h, 5.0) + 24.0 * c / pow(hd, 5.0);
+    }
+}
+
 void or_coeffs(const or_model *M, double h, double *f0, double *f0p, double *f1, double *f1p)
 {
     if (M->kind == OR_LINEAR) {
         *f0 = M->c0; *f0p = 0.0; *f1 = M->c1; *f1p = 0.0;
+        return;
+    }
+    if (M->kind == OR_NLC || M->kind == OR_POLYMER) {
+        /* eq. GeneralDisPreForm read as f0 = C h^3, f1 = h^3 Pi'(h) (the form that gives the
+         * growth rates printed with Fig. dispersion_curves) */
+        double Pi, Pip, Pipp;
+        or_disjoining(M, h, &Pi, &Pip, &Pipp);
+        *f0 = M->cap * h * h * h;
+        *f0p = 3.0 * M->cap * h * h;
+        *f1 = h * h * h * Pip;
+        *f1p = 3.0 * h * h * Pip + h * h * h * Pipp;
         return;
     }
     const double n = M->n, m = M->m, b = M->b;
