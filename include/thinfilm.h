@@ -3,8 +3,10 @@
  * ADI-Newton time step for the thin-film equation
  *
  *     h_t + div[ f0(h) grad lap h + f1(h) grad h ] = 0,
- *     f0 = h^3,  f1 = kappa h^3 f'(h),  f(h) = (b/h)^n - (b/h)^m,
+ *     f0 = h^3,  f1 = kappa h^3 f'(h),  f(h) = (b/h)^n - (b/h)^m   (power law),
  *
+ * or f0 = C h^3, f1 = h^3 Pi'(h) with the disjoining pressure Pi of the nematic liquid
+ * crystal or the polymer film model (tf_set_model_nlc, tf_set_model_polymer),
  * on a cell-centred grid with no-flux boundaries (u_n = u_nnn = 0), following
  * M.-A. Y.-H. Lam, L. J. Cummings, L. Kondic, "Computing dynamics of thin films via
  * large scale GPU-based simulations", arXiv:1806.10550:
@@ -84,6 +86,22 @@ tf_status tf_destroy(tf_grid *g);
  * with the power-law term of eq. DisjPressNLC). b > 0; n and m integral with
  * 16 >= n > m >= 1 (TF_EINVAL otherwise). kappa may have any sign. */
 tf_status tf_set_model(tf_grid *g, double kappa, double b, double n, double m);
+/* Nematic liquid crystal model (Sec. "Thin Film Models", eqs. GeneralDisPreForm,
+ * DisjPressNLC, mh_model): f0 = C h^3, f1 = h^3 Pi'(h) (without the division by C that
+ * eq. GeneralDisPreForm prints: this is the reading under which the growth rates printed
+ * with Fig. dispersion_curves follow),
+ *     Pi = K[(b/h)^3 - (b/h)^2] + (N/2) (m(h)/h)^2,  m = g(h) h^2 / (h^2 + beta^2),
+ *     g = (1 + tanh((h - 2b)/w)) / 2.
+ * The paper's parameters (eq. NLC_paras): C = 0.0857, K = 36, N = 1.67, beta = 1,
+ * w = 0.05, b = 0.01. Needs finite values with C, w, b > 0 and K, N >= 0 (TF_EINVAL
+ * otherwise). Replaces any model set before; invalidates the bound state's check. */
+tf_status tf_set_model_nlc(tf_grid *g, double C, double K, double N, double beta, double w, double b);
+/* Polymer film model (Sec. "Thin Film Models", eqs. GeneralDisPreForm, DisjPressPolymer):
+ * f0 = C h^3, f1 = h^3 Pi'(h) (same reading as above), Pi = -psi'(h),
+ *     psi = Cst h^-8 - Aox / (12 pi h^2) + (Aox - Asi) / (12 pi (h + d)^2).
+ * The paper's parameters (eq. Polymer_scales): C = 0.00581, Cst = 1.181, Aox = 41.25,
+ * Asi = -243.75, d = 191. Needs finite values with C > 0, d >= 0 (TF_EINVAL otherwise). */
+tf_status tf_set_model_polymer(tf_grid *g, double C, double Cst, double Aox, double Asi, double d);
 tf_status tf_set_scheme(tf_grid *g, const tf_scheme *s);
 tf_status tf_get_scheme(const tf_grid *g, tf_scheme *s);
 /* 1: fill tf_step_info.mass / hmin after every accepted step (one extra read of h). */
@@ -165,7 +183,7 @@ tf_status tf_ensemble_film_info(const tf_ensemble *e, int film, tf_step_info *in
  * max|dmu| <= tol max|mu| (at most max_iter iterations; TF_ENOCONV otherwise), then
  * writes lambda^n = mu - (1-theta) dt J_D(u^n)^T mu into lambda_inout and adds
  * -dt mu . [theta dD/dkappa(u^{n+1}) + (1-theta) dD/dkappa(u^n)] to *dL_dkappa_accum
- * (host, nullable). h_n, h_np1: the two time levels (device, nx*ny each, unchanged).
+ * (host, nullable; power-law model only, TF_EINVAL for the NLC and polymer models). h_n, h_np1: the two time levels (device, nx*ny each, unchanged).
  * iters_out (host, nullable): Richardson iterations used. */
 tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, double dt, double *lambda_inout,
                           double *dL_dkappa_accum, double tol, int max_iter, int *iters_out);

@@ -803,6 +803,8 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
         return afail(TF_EINVAL, "NULL argument");
     if (!tf_detail::grid_view(g, &v)) return afail(TF_ESTATE, "model not set");
     if (!(dt > 0.0) || !(tol > 0.0) || max_iter < 1) return afail(TF_EINVAL, "need dt > 0, tol > 0, max_iter >= 1");
+    if (dL_dkappa_accum != nullptr && v.M.kind != tf::MODEL_POWER)
+        return afail(TF_EINVAL, "dL/dkappa is defined for the power-law model only");
     AdjBuffers *Bp;
     tf_status st = get_adj(g, v.nx, v.ny, &Bp);
     if (st != TF_OK) return st;

@@ -114,8 +114,9 @@ tf::PassParams base_params(const tf_grid *g, double dt)
     P.nx = g->nx;
     P.ny = g->ny;
     P.ids2 = 1.0 / (g->ds * g->ds);
+    P.f0s = P.ids2 * g->M.cap;
     P.ka = 0.5 * g->S.theta * dt * P.ids2;
-    P.K0 = 3.0 * P.ka * P.ids2;
+    P.K0 = 3.0 * P.ka * P.ids2 * g->M.cap;
     P.K1 = P.ka * g->M.Dn;
     P.M = g->M;
     P.res_spread = tf::RES_SPREAD;
@@ -439,6 +440,51 @@ tf_status tf_set_model(tf_grid *g, double kappa, double b, double n, double m)
     M.Dn = kappa * n * (n - 2.0) * std::pow(b, n);
     M.Dm = kappa * m * (m - 2.0) * std::pow(b, m);
     M.p32 = (M.n == 3 && M.m == 2);
+    M.kind = tf::MODEL_POWER;
+    M.cap = 1.0;
+    g->M = M;
+    g->model_set = true;
+    g->state_ok = false;
+    return TF_OK;
+}
+
+tf_status tf_set_model_nlc(tf_grid *g, double C, double K, double N, double beta, double w, double b)
+{
+    if (g == nullptr) return fail(TF_EINVAL, "grid is NULL");
+    const double v[6] = {C, K, N, beta, w, b};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(TF_EINVAL, "NLC parameters must be finite");
+    if (!(C > 0.0) || !(w > 0.0) || !(b > 0.0)) return fail(TF_EINVAL, "need C > 0, w > 0 and b > 0");
+    if (!(K >= 0.0) || !(N >= 0.0)) return fail(TF_EINVAL, "need K >= 0 and N >= 0");
+    tf::Model M{};
+    M.kind = tf::MODEL_NLC;
+    M.cap = C;
+    M.K = K;
+    M.N = N;
+    M.beta2 = beta * beta;
+    M.w = w;
+    M.b = b;
+    g->M = M;
+    g->model_set = true;
+    g->state_ok = false;
+    return TF_OK;
+}
+
+tf_status tf_set_model_polymer(tf_grid *g, double C, double Cst, double Aox, double Asi, double d)
+{
+    if (g == nullptr) return fail(TF_EINVAL, "grid is NULL");
+    const double v[5] = {C, Cst, Aox, Asi, d};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(TF_EINVAL, "polymer parameters must be finite");
+    if (!(C > 0.0) || !(d >= 0.0)) return fail(TF_EINVAL, "need C > 0 and d >= 0");
+    tf::Model M{};
+    M.kind = tf::MODEL_POLYMER;
+    M.cap = C;
+    // Pi = -psi' = 8 Cst h^-9 - (Aox/(6 pi)) h^-3 + ((Aox - Asi)/(6 pi)) (h+d)^-3
+    M.C8 = 8.0 * Cst;
+    M.a2 = Aox / (6.0 * M_PI);
+    M.c2 = (Aox - Asi) / (6.0 * M_PI);
+    M.d = d;
     g->M = M;
     g->model_set = true;
     g->state_ok = false;

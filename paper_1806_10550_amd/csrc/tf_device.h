@@ -27,21 +27,51 @@ __device__ __forceinline__ double ipow(double r, double h, int k)
     return acc;
 }
 
-// f0 = h^3, f0' = 3h^2, f1 = kappa h^3 f'(h), f1' (see Model).
+// Pi'(h) and Pi''(h) of the NLC and polymer models (see Model), r = 1/h. NLC, with
+// q = m(h)/h = g(h) s(h), s = h / (h^2 + beta^2):
+//   Pi'  = K(-3 b^3 h^-4 + 2 b^2 h^-3) + N q q',
+//   Pi'' = K(12 b^3 h^-5 - 6 b^2 h^-4) + N (q'^2 + q q'').
+__device__ __forceinline__ void disjoining_derivs(const Model &M, double h, double r, double &pip, double &pipp)
+{
+    const double r2 = r * r, r4 = r2 * r2, r5 = r4 * r;
+    if (M.kind == MODEL_NLC) {
+        const double z = (h - 2.0 * M.b) / M.w;
+        const double th = tanh(z), s2 = 1.0 - th * th;
+        const double g = 0.5 * (1.0 + th), gp = 0.5 * s2 / M.w, gpp = -s2 * th / (M.w * M.w);
+        const double rd = rcp(h * h + M.beta2);
+        const double sv = h * rd, sp = (M.beta2 - h * h) * rd * rd, spp = 2.0 * h * (h * h - 3.0 * M.beta2) * rd * rd * rd;
+        const double q = g * sv, qp = gp * sv + g * sp, qpp = gpp * sv + 2.0 * gp * sp + g * spp;
+        const double b2 = M.b * M.b, b3 = b2 * M.b;
+        pip = M.K * (-3.0 * b3 * r4 + 2.0 * b2 * r2 * r) + M.N * q * qp;
+        pipp = M.K * (12.0 * b3 * r5 - 6.0 * b2 * r4) + M.N * (qp * qp + q * qpp);
+    } else {
+        const double e = rcp(h + M.d), e2 = e * e, e4 = e2 * e2;
+        const double r10 = r5 * r5;
+        pip = -9.0 * M.C8 * r10 + 3.0 * M.a2 * r4 - 3.0 * M.c2 * e4;
+        pipp = 90.0 * M.C8 * r10 * r - 12.0 * M.a2 * r5 + 12.0 * M.c2 * e4 * e;
+    }
+}
+
+// f0 = cap h^3, f0' = 3 cap h^2, f1 = h^3 Pi'(h), f1' = 3 h^2 Pi' + h^3 Pi'' (see Model).
 template <bool P32>
 __device__ __forceinline__ void model_coefs(const Model &M, double u, double &f0, double &f1,
                                             double &f0p, double &f1p)
 {
     const double r = rcp(u);
     const double u2 = u * u;
-    f0 = u2 * u;
-    f0p = 3.0 * u2;
+    f0 = M.cap * (u2 * u);
+    f0p = 3.0 * M.cap * u2;
     if (P32) {
         f1 = M.Cm - M.Cn * r;
         f1p = M.Dn * (r * r);
-    } else {
+    } else if (M.kind == MODEL_POWER) {
         f1 = M.Cm * ipow(r, u, M.m - 2) - M.Cn * ipow(r, u, M.n - 2);
         f1p = M.Dn * ipow(r, u, M.n - 1) - M.Dm * ipow(r, u, M.m - 1);
+    } else {
+        double pip, pipp;
+        disjoining_derivs(M, u, r, pip, pipp);
+        f1 = (u2 * u) * pip;
+        f1p = 3.0 * u2 * pip + (u2 * u) * pipp;
     }
 }
 

@@ -160,6 +160,8 @@ tf_status tf_ensemble_create(int nfilms, const int *nx, const int *ny, const dou
         M.Dn = kappa[f] * n * (n - 2.0) * std::pow(b, n);
         M.Dm = kappa[f] * m * (m - 2.0) * std::pow(b, m);
         M.p32 = e->p32;
+        M.kind = tf::MODEL_POWER;
+        M.cap = 1.0;
         d.M = M;
         d.off = e->ncells;
         d.roff = e->nrec;

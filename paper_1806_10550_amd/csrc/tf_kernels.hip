@@ -63,7 +63,7 @@ __device__ __forceinline__ double lane_prev(double v) { return dpp_shift(v, 0x13
 // Per-cell quantities of the sweeps, scaled so that each face record takes few
 // operations (ka = c / (2 ds^2), c = theta dt):
 //   lap = u_E + u_W + u_N + u_S - 4u      (ds^2 times the 5-point Laplacian)
-//   f0  = h^3 / ds^2,   f1 = kappa h^3 f'(h)
+//   f0  = cap h^3 / ds^2,   f1 = h^3 Pi'(h)
 //   g0  = ka f0'(h) / ds^2,   g1 = ka f1'(h)
 struct CellS {
     double u, lap, f0, f1, g0, g1;
@@ -85,15 +85,20 @@ __device__ __forceinline__ CellS cell_s(const double *sU, const PassParams &p, i
     c.lap = __builtin_fma(-4.0, c.u, (xp + xm) + (yp + ym));
     const double r = rcp(c.u);
     const double u2 = c.u * c.u;
-    c.f0 = (u2 * c.u) * p.ids2;
+    c.f0 = (u2 * c.u) * p.f0s;
     c.g0 = p.K0 * u2;
     if (P32) {
         c.f1 = __builtin_fma(-p.M.Cn, r, p.M.Cm);
         c.g1 = p.K1 * (r * r);
-    } else {
+    } else if (p.M.kind == MODEL_POWER) {
         const Model &M = p.M;
         c.f1 = M.Cm * ipow(r, c.u, M.m - 2) - M.Cn * ipow(r, c.u, M.n - 2);
         c.g1 = p.ka * (M.Dn * ipow(r, c.u, M.n - 1) - M.Dm * ipow(r, c.u, M.m - 1));
+    } else {
+        double pip, pipp;
+        disjoining_derivs(p.M, c.u, r, pip, pipp);
+        c.f1 = (u2 * c.u) * pip;
+        c.g1 = p.ka * (3.0 * u2 * pip + (u2 * c.u) * pipp);
     }
     return c;
 }
@@ -509,8 +514,9 @@ __global__ void TF_PASS_ATTR k_pass_ens(EnsParams e)
     p.nx = d.nx;
     p.ny = d.ny;
     p.ids2 = 1.0 / (d.ds * d.ds);
+    p.f0s = p.ids2 * d.M.cap;
     p.ka = 0.5 * e.theta * s->dt * p.ids2;
-    p.K0 = 3.0 * p.ka * p.ids2;
+    p.K0 = 3.0 * p.ka * p.ids2 * d.M.cap;
     p.K1 = p.ka * d.M.Dn;
     p.M = d.M;
     p.u = B[s->it] + d.off;

@@ -58,6 +58,8 @@ def lib():
         L.tf_create.argtypes = [C.c_int, C.c_int, D, P, C.POINTER(P)]
         L.tf_destroy.argtypes = [P]
         L.tf_set_model.argtypes = [P, D, D, D, D]
+        L.tf_set_model_nlc.argtypes = [P, D, D, D, D, D, D]
+        L.tf_set_model_polymer.argtypes = [P, D, D, D, D, D]
         L.tf_set_scheme.argtypes = [P, C.POINTER(Scheme)]
         L.tf_get_scheme.argtypes = [P, C.POINTER(Scheme)]
         L.tf_set_diagnostics.argtypes = [P, C.c_int]
@@ -149,6 +151,16 @@ class Grid:
         _check(lib().tf_set_model(self._h, float(kappa), float(b), float(n), float(m)))
         return self
 
+    def set_model_nlc(self, C=0.0857, K=36.0, N=1.67, beta=1.0, w=0.05, b=0.01):
+        """NLC model (eqs. DisjPressNLC, mh_model); defaults are eq. NLC_paras."""
+        _check(lib().tf_set_model_nlc(self._h, *(float(x) for x in (C, K, N, beta, w, b))))
+        return self
+
+    def set_model_polymer(self, C=0.00581, Cst=1.181, Aox=41.25, Asi=-243.75, d=191.0):
+        """Polymer model (eq. DisjPressPolymer); defaults are eq. Polymer_scales."""
+        _check(lib().tf_set_model_polymer(self._h, *(float(x) for x in (C, Cst, Aox, Asi, d))))
+        return self
+
     def set_scheme(self, **kw):
         s = default_scheme(**kw)
         _check(lib().tf_set_scheme(self._h, C.byref(s)))
@@ -213,14 +225,16 @@ class Grid:
         _check(lib().tf_flux_divergence(self._h, _ptr(u), _ptr(out)))
         return out
 
-    def adjoint_step(self, h_n, h_np1, dt: float, lam, tol: float = 1e-13, max_iter: int = 2000):
+    def adjoint_step(self, h_n, h_np1, dt: float, lam, tol: float = 1e-13, max_iter: int = 2000,
+                     dkappa: bool = True):
         """lam (device, in/out): lambda^{n+1} -> lambda^n. Returns (dL/dkappa contribution,
-        Richardson iterations)."""
+        Richardson iterations); the contribution is None with dkappa=False (required for the
+        NLC and polymer models, which have no kappa)."""
         g = C.c_double(0.0)
         it = C.c_int(0)
-        _check(lib().tf_adjoint_step(self._h, _ptr(h_n), _ptr(h_np1), float(dt), _ptr(lam), C.byref(g),
-                                     float(tol), int(max_iter), C.byref(it)))
-        return g.value, it.value
+        _check(lib().tf_adjoint_step(self._h, _ptr(h_n), _ptr(h_np1), float(dt), _ptr(lam),
+                                     C.byref(g) if dkappa else None, float(tol), int(max_iter), C.byref(it)))
+        return (g.value if dkappa else None), it.value
 
     def jacobian_apply_t(self, u, mu, out):
         _check(lib().tf_jacobian_apply_t(self._h, _ptr(u), _ptr(mu), _ptr(out)))
