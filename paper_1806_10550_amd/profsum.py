@@ -72,6 +72,23 @@ def counter_means(d, counter):
     return {k: statistics.mean(v) for k, v in per.items()}, {k: len(v) for k, v in per.items()}
 
 
+# the counter runs this record summarises (repo root R on the GPU machine, run from /tmp with
+# TMPDIR=/tmp); one counter per pass
+COMMANDS = [
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_fetch -o run -- "
+    "python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_write -o run -- "
+    "python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/copy_fetch -o run -- "
+    "python $R/bench.py --calibrate-copy",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/copy_write -o run -- "
+    "python $R/bench.py --calibrate-copy",
+    "python -m paper_1806_10550_amd.profsum traffic --fetch gpurun_out/pmc_fetch --write gpurun_out/pmc_write "
+    "--copy-fetch gpurun_out/copy_fetch --copy-write gpurun_out/copy_write --copy-bytes 1073741824 "
+    "--hash $(python bench.py --print-hash)",
+]
+
+
 def traffic(a):
     fetch, nf = counter_means(a.fetch, "FETCH_SIZE")
     write, nw = counter_means(a.write, "WRITE_SIZE")
@@ -82,6 +99,7 @@ def traffic(a):
     cw_kib = max(cw.values())
     known_kib = a.copy_bytes / 1024.0
     out = {
+        "commands": COMMANDS,
         "kernel_hash": a.hash,
         "copy_bytes": a.copy_bytes,
         "copy_fetch_kib": cf_kib,
