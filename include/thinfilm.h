@@ -6,7 +6,8 @@
  *     f0 = h^3,  f1 = kappa h^3 f'(h),  f(h) = (b/h)^n - (b/h)^m   (power law),
  *
  * or f0 = C h^3, f1 = h^3 Pi'(h) with the disjoining pressure Pi of the nematic liquid
- * crystal or the polymer film model (tf_set_model_nlc, tf_set_model_polymer),
+ * crystal or the polymer film model (tf_set_model_nlc, tf_set_model_polymer), or the linear
+ * test model f0 = c0, f1 = c1 (tf_set_model_linear),
  * on a cell-centred grid with no-flux boundaries (u_n = u_nnn = 0), following
  * M.-A. Y.-H. Lam, L. J. Cummings, L. Kondic, "Computing dynamics of thin films via
  * large scale GPU-based simulations", arXiv:1806.10550:
@@ -86,6 +87,11 @@ tf_status tf_destroy(tf_grid *g);
  * with the power-law term of eq. DisjPressNLC). b > 0; n and m integral with
  * 16 >= n > m >= 1 (TF_EINVAL otherwise). kappa may have any sign. */
 tf_status tf_set_model(tf_grid *g, double kappa, double b, double n, double m);
+/* Linear test model (Sec. "Thin Film Models"): f0 = c0, f1 = c1, constants, so that the
+ * step is linear in h (the paper's validation runs use c0 = 1, c1 = 1: q_m = 1/sqrt(2),
+ * omega_m = 1/4). Needs finite c0 > 0 and c1 (TF_EINVAL otherwise). The positivity
+ * check on h (TF_ENONPOS) still applies. */
+tf_status tf_set_model_linear(tf_grid *g, double c0, double c1);
 /* Nematic liquid crystal model (Sec. "Thin Film Models", eqs. GeneralDisPreForm,
  * DisjPressNLC, mh_model): f0 = C h^3, f1 = h^3 Pi'(h) (without the division by C that
  * eq. GeneralDisPreForm prints: this is the reading under which the growth rates printed
@@ -102,6 +108,11 @@ tf_status tf_set_model_nlc(tf_grid *g, double C, double K, double N, double beta
  * The paper's parameters (eq. Polymer_scales): C = 0.00581, Cst = 1.181, Aox = 41.25,
  * Asi = -243.75, d = 191. Needs finite values with C > 0, d >= 0 (TF_EINVAL otherwise). */
 tf_status tf_set_model_polymer(tf_grid *g, double C, double Cst, double Aox, double Asi, double d);
+/* The grid's model coefficients at n thicknesses: out[4k + 0..3] = f0, f0', f1, f1' at h[k]
+ * (eq. GeneralDisPreForm; these give the linear growth rate sigma(q) = q^2 (f1 - f0 q^2) of
+ * a flat film, Sec. "Linear Stability Analysis"). h: device, n doubles (> 0); out: device,
+ * 4n doubles. Evaluated by the same device code as the sweeps. TF_ESTATE without a model. */
+tf_status tf_model_coeffs(tf_grid *g, const double *h, int n, double *out);
 tf_status tf_set_scheme(tf_grid *g, const tf_scheme *s);
 tf_status tf_get_scheme(const tf_grid *g, tf_scheme *s);
 /* 1: fill tf_step_info.mass / hmin after every accepted step (one extra read of h). */
@@ -183,7 +194,7 @@ tf_status tf_ensemble_film_info(const tf_ensemble *e, int film, tf_step_info *in
  * max|dmu| <= tol max|mu| (at most max_iter iterations; TF_ENOCONV otherwise), then
  * writes lambda^n = mu - (1-theta) dt J_D(u^n)^T mu into lambda_inout and adds
  * -dt mu . [theta dD/dkappa(u^{n+1}) + (1-theta) dD/dkappa(u^n)] to *dL_dkappa_accum
- * (host, nullable; power-law model only, TF_EINVAL for the NLC and polymer models). h_n, h_np1: the two time levels (device, nx*ny each, unchanged).
+ * (host, nullable; power-law model only, TF_EINVAL for the linear, NLC and polymer models). h_n, h_np1: the two time levels (device, nx*ny each, unchanged).
  * iters_out (host, nullable): Richardson iterations used. */
 tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, double dt, double *lambda_inout,
                           double *dL_dkappa_accum, double tol, int max_iter, int *iters_out);

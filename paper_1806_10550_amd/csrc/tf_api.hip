@@ -448,6 +448,20 @@ tf_status tf_set_model(tf_grid *g, double kappa, double b, double n, double m)
     return TF_OK;
 }
 
+tf_status tf_set_model_linear(tf_grid *g, double c0, double c1)
+{
+    if (g == nullptr) return fail(TF_EINVAL, "grid is NULL");
+    if (!(c0 > 0.0) || !std::isfinite(c0) || !std::isfinite(c1)) return fail(TF_EINVAL, "need finite c0 > 0 and c1");
+    tf::Model M{};
+    M.kind = tf::MODEL_LINEAR;
+    M.cap = c0;
+    M.Cm = c1;
+    g->M = M;
+    g->model_set = true;
+    g->state_ok = false;
+    return TF_OK;
+}
+
 tf_status tf_set_model_nlc(tf_grid *g, double C, double K, double N, double beta, double w, double b)
 {
     if (g == nullptr) return fail(TF_EINVAL, "grid is NULL");
@@ -589,6 +603,17 @@ tf_status tf_flux_divergence(tf_grid *g, const double *u, double *out)
     const double ids = 1.0 / g->ds;
     const hipError_t e =
         tf::launch_flux_divergence(g->nx, g->ny, ids, ids * ids, g->M, u, 0.0, 1.0, nullptr, out, g->stream);
+    if (e != hipSuccess) return fail(TF_EDEVICE, hipGetErrorString(e));
+    TF_HIP(hipStreamSynchronize(g->stream));
+    return TF_OK;
+}
+
+tf_status tf_model_coeffs(tf_grid *g, const double *h, int n, double *out)
+{
+    if (g == nullptr || (n > 0 && (h == nullptr || out == nullptr))) return fail(TF_EINVAL, "NULL argument");
+    if (n < 0) return fail(TF_EINVAL, "n must be >= 0");
+    if (!g->model_set) return fail(TF_ESTATE, "model not set");
+    const hipError_t e = tf::launch_model_coeffs(g->M, h, n, out, g->stream);
     if (e != hipSuccess) return fail(TF_EDEVICE, hipGetErrorString(e));
     TF_HIP(hipStreamSynchronize(g->stream));
     return TF_OK;

@@ -52,11 +52,19 @@ __device__ __forceinline__ void disjoining_derivs(const Model &M, double h, doub
     }
 }
 
-// f0 = cap h^3, f0' = 3 cap h^2, f1 = h^3 Pi'(h), f1' = 3 h^2 Pi' + h^3 Pi'' (see Model).
+// f0 = cap h^3, f0' = 3 cap h^2, f1 = h^3 Pi'(h), f1' = 3 h^2 Pi' + h^3 Pi'' (see Model);
+// f0 = c0, f1 = c1 for the linear model.
 template <bool P32>
 __device__ __forceinline__ void model_coefs(const Model &M, double u, double &f0, double &f1,
                                             double &f0p, double &f1p)
 {
+    if (!P32 && M.kind == MODEL_LINEAR) {
+        f0 = M.cap;
+        f1 = M.Cm;
+        f0p = 0.0;
+        f1p = 0.0;
+        return;
+    }
     const double r = rcp(u);
     const double u2 = u * u;
     f0 = M.cap * (u2 * u);

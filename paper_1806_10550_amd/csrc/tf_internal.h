@@ -44,18 +44,20 @@ __host__ __device__ inline int seg_start(int q, int n)
 //   of r = 1/h:
 //     f1  = Cm r^(m-2) - Cn r^(n-2),  Cm = kappa m b^m, Cn = kappa n b^n
 //     f1' = Dn r^(n-1) - Dm r^(m-1),  Dn = kappa n (n-2) b^n, Dm = kappa m (m-2) b^m
+// MODEL_LINEAR: the linear test model f0 = c0, f1 = c1 (Sec. "Thin Film Models"); c0 is held
+//   in cap, c1 in Cm.
 // MODEL_NLC: Pi = K[(b/h)^3 - (b/h)^2] + N/2 (m(h)/h)^2, m(h) = g(h) h^2/(h^2 + beta^2),
 //   g = (1 + tanh((h - 2b)/w))/2 (eqs. DisjPressNLC, mh_model).
 // MODEL_POLYMER: Pi = -psi', psi = Cst h^-8 - Aox/(12 pi h^2) + (Aox - Asi)/(12 pi (h+d)^2)
 //   (eq. DisjPressPolymer), stored as Pi = C8 h^-9 - a2 h^-3 + c2 (h+d)^-3.
-enum ModelKind { MODEL_POWER = 0, MODEL_NLC = 2, MODEL_POLYMER = 3 };
+enum ModelKind { MODEL_POWER = 0, MODEL_LINEAR = 1, MODEL_NLC = 2, MODEL_POLYMER = 3 };
 struct Model {
     double kappa, b;
     int n, m;
     double Cn, Cm, Dn, Dm;
     bool p32; // power law with n == 3 && m == 2: f1 = Cm - Cn r, f1' = Dn r^2
     int kind;
-    double cap;                // C in f0 = C h^3
+    double cap;                // C in f0 = C h^3 (c0 of the linear model)
     double K, N, beta2, w;     // NLC (with b)
     double C8, a2, c2, d;      // polymer
 };
@@ -64,7 +66,7 @@ struct Model {
 struct PassParams {
     int nx, ny;
     double ids2;        // 1/ds^2
-    double f0s;         // cap / ds^2 (scale of h^3 in the cell's f0)
+    double f0s;         // cap / ds^2 (scale of h^3 in the cell's f0; the linear model's f0 / ds^2)
     double ka;          // c / (2 ds^2) with c = theta dt
     double K0, K1;      // 3 ka cap / ds^2 (scale of h^2 in g0) and ka Dn (of r^2 in g1, n=3, m=2)
     Model M;
@@ -129,6 +131,7 @@ enum ResultFlag { FLAG_NONPOS = 1, FLAG_NAN = 2 };
 hipError_t launch_flux_divergence_f1(int nx, int ny, double ids, double ids2, const Model &M, const double *u,
                                      double *out, hipStream_t s);
 hipError_t launch_pass(int dir, bool solve, const PassParams &p, hipStream_t s);
+hipError_t launch_model_coeffs(const Model &M, const double *h, int n, double *out, hipStream_t s);
 hipError_t launch_chain(const ChainParams &c, hipStream_t s);
 hipError_t launch_flux_divergence(int nx, int ny, double ids, double ids2, const Model &M,
                                   const double *u, double alpha, double beta, const double *add,

@@ -83,6 +83,13 @@ __device__ __forceinline__ CellS cell_s(const double *sU, const PassParams &p, i
         yp = uat<DIR>(sU, l + 1, q); ym = uat<DIR>(sU, l - 1, q);
     }
     c.lap = __builtin_fma(-4.0, c.u, (xp + xm) + (yp + ym));
+    if (!P32 && p.M.kind == MODEL_LINEAR) {
+        c.f0 = p.f0s;
+        c.g0 = 0.0;
+        c.f1 = p.M.Cm;
+        c.g1 = 0.0;
+        return c;
+    }
     const double r = rcp(c.u);
     const double u2 = c.u * c.u;
     c.f0 = (u2 * c.u) * p.f0s;
@@ -1025,6 +1032,27 @@ hipError_t launch_flux_divergence(int nx, int ny, double ids, double ids2, const
     const dim3 grid((nx + 63) / 64, (ny + 3) / 4), block(256);
     if (M.p32) k_flux_divergence<true, false><<<grid, block, 0, s>>>(nx, ny, ids, ids2, M, u, alpha, beta, add, out);
     else k_flux_divergence<false, false><<<grid, block, 0, s>>>(nx, ny, ids, ids2, M, u, alpha, beta, add, out);
+    return hipGetLastError();
+}
+
+// f0, f0', f1, f1' of the model at n thicknesses (out[4k + 0..3]).
+__global__ void __launch_bounds__(256) k_model_coeffs(Model M, const double *__restrict__ h, int n,
+                                                      double *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double f0, f1, f0p, f1p;
+    model_coefs<false>(M, h[k], f0, f1, f0p, f1p);
+    out[4 * k + 0] = f0;
+    out[4 * k + 1] = f0p;
+    out[4 * k + 2] = f1;
+    out[4 * k + 3] = f1p;
+}
+
+hipError_t launch_model_coeffs(const Model &M, const double *h, int n, double *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_model_coeffs<<<(n + 255) / 256, 256, 0, s>>>(M, h, n, out);
     return hipGetLastError();
 }
 

@@ -58,6 +58,8 @@ def lib():
         L.tf_create.argtypes = [C.c_int, C.c_int, D, P, C.POINTER(P)]
         L.tf_destroy.argtypes = [P]
         L.tf_set_model.argtypes = [P, D, D, D, D]
+        L.tf_set_model_linear.argtypes = [P, D, D]
+        L.tf_model_coeffs.argtypes = [P, P, C.c_int, P]
         L.tf_set_model_nlc.argtypes = [P, D, D, D, D, D, D]
         L.tf_set_model_polymer.argtypes = [P, D, D, D, D, D]
         L.tf_set_scheme.argtypes = [P, C.POINTER(Scheme)]
@@ -150,6 +152,18 @@ class Grid:
     def set_model(self, kappa=10.0, b=0.1, n=3, m=2):
         _check(lib().tf_set_model(self._h, float(kappa), float(b), float(n), float(m)))
         return self
+
+    def set_model_linear(self, c0=1.0, c1=1.0):
+        """Linear test model f0 = c0, f1 = c1 (Sec. "Thin Film Models")."""
+        _check(lib().tf_set_model_linear(self._h, float(c0), float(c1)))
+        return self
+
+    def model_coeffs(self, h, out):
+        """out[k] = (f0, f0', f1, f1') at h[k]; h: (n,) and out: (n, 4) float64 CUDA tensors."""
+        if out.numel() != 4 * h.numel():
+            raise ValueError("out must hold 4 values per thickness")
+        _check(lib().tf_model_coeffs(self._h, _ptr(h), int(h.numel()), _ptr(out)))
+        return out
 
     def set_model_nlc(self, C=0.0857, K=36.0, N=1.67, beta=1.0, w=0.05, b=0.01):
         """NLC model (eqs. DisjPressNLC, mh_model); defaults are eq. NLC_paras."""

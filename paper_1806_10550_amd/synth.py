@@ -55,6 +55,17 @@ def cosine_film(nx: int, ny: int, kx: int, ky: int, h0: float = 1.0, amp: float 
     return h0 * (1.0 + amp * np.outer(y, x))
 
 
+def wave_film(n: int, P: float, q: float, h0: float = 1.0, ex: float = 0.1, ey: float = 0.1):
+    """Initial condition of eq. IC_LinearWave: h0 (1 + ex cos(q x) + ey cos(q y)) at the cell
+    centres of n x n cells on the square [0, P lam]^2, lam = 2 pi / q. Returns (h, ds).
+    The printed argument pi x / lam is read as q x, so that q is the wavenumber of the
+    perturbation; both forms have zero slope at the walls for integer P."""
+    L = P * 2.0 * math.pi / q
+    ds = L / n
+    c = np.cos(q * (np.arange(n) + 0.5) * ds)
+    return h0 * (1.0 + ex * c[None, :] + ey * c[:, None]), ds
+
+
 def gaussian_depression(h: np.ndarray, ds: float, depth: float, width: float) -> np.ndarray:
     """h - depth * exp(-r^2 / width^2) about the domain centre (r measured between
     cell centres)."""

@@ -1,10 +1,13 @@
-"""GPU path with the NLC and polymer models (f0 = C h^3, f1 = h^3 Pi'(h); eqs.
-GeneralDisPreForm, DisjPressNLC, mh_model, DisjPressPolymer) against the CPU oracle.
+"""GPU path with the paper's other models against the CPU oracle: NLC and polymer
+(f0 = C h^3, f1 = h^3 Pi'(h); eqs. GeneralDisPreForm, DisjPressNLC, mh_model,
+DisjPressPolymer) and the linear test model f0 = c0 = 1, f1 = c1 = 1 (Sec. "Thin Film
+Models").
 
-Inputs: flat films at the thicknesses of Fig. dispersion_curves (NLC H0 = 0.5, polymer
-H0 = 3.9) with uniform noise, on grids of ds = lambda_m / 16; plus films that reach into
-the precursor range of each disjoining pressure (NLC down to 1.2 b, where the tanh switch
-of m(h) acts; polymer down to h = 2) so that every term of Pi' and Pi'' is exercised.
+Inputs: flat films at the thicknesses of Fig. dispersion_curves (linear H0 = 1, NLC
+H0 = 0.5, polymer H0 = 3.9) with uniform noise, on grids of ds = lambda_m / 16; plus films
+that reach into the precursor range of each disjoining pressure (NLC down to 1.2 b, where
+the tanh switch of m(h) acts; polymer down to h = 2) so that every term of Pi' and Pi'' is
+exercised.
 Tolerances are those of the power-law parity tests.
 """
 import math
@@ -19,9 +22,10 @@ from paper_1806_10550_amd.lib import Grid, TFError
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
-# (H0, ds = lambda_m / 16, dt) per model; lambda_m = 2 pi / q_m at H0 (q_m = 1.482 NLC,
-# 1.5599 polymer)
+# (H0, ds = lambda_m / 16, dt) per model; lambda_m = 2 pi / q_m at H0 (q_m = 1/sqrt(2)
+# linear, 1.482 NLC, 1.5599 polymer)
 CASES = {
+    "linear": (1.0, 2 * math.pi * math.sqrt(2.0) / 16, 0.1),
     "nlc": (0.5, 2 * math.pi / 1.482 / 16, 0.5),
     "polymer": (3.9, 2 * math.pi / 1.5599 / 16, 0.01),
 }
@@ -32,7 +36,12 @@ def gpu(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
+KINDS = ["linear", "nlc", "polymer"]
+
+
 def omodel(orc, kind):
+    if kind == "linear":
+        return orc.Model(kind=orc.LINEAR, c0=1.0, c1=1.0)
     return getattr(orc.Model, kind)()
 
 
@@ -47,11 +56,11 @@ def film(kind, nx, ny, seed, wide=False):
     h0 = CASES[kind][0]
     if not wide:
         return synth.noise_film(nx, ny, seed=seed, h0=h0, amp=0.01 * h0)
-    lo, hi = (0.012, 0.6) if kind == "nlc" else (2.0, 8.0)
+    lo, hi = {"linear": (0.5, 1.5), "nlc": (0.012, 0.6), "polymer": (2.0, 8.0)}[kind]
     return lo + (hi - lo) * np.random.default_rng(seed).uniform(0.0, 1.0, (ny, nx))
 
 
-@pytest.mark.parametrize("kind", ["nlc", "polymer"])
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("wide", [False, True])
 @pytest.mark.parametrize("nx,ny", SHAPES)
 def test_flux_divergence(orc, kind, wide, nx, ny):
@@ -65,7 +74,7 @@ def test_flux_divergence(orc, kind, wide, nx, ny):
     assert err <= 1e-12 * np.max(np.abs(ref)), err
 
 
-@pytest.mark.parametrize("kind", ["nlc", "polymer"])
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("nx,ny", SHAPES)
 def test_newton_iteration(orc, kind, nx, ny):
     _, ds, dt = CASES[kind]
@@ -89,7 +98,7 @@ def test_newton_iteration(orc, kind, nx, ny):
         uk_g = out.clone()
 
 
-@pytest.mark.parametrize("kind", ["nlc", "polymer"])
+@pytest.mark.parametrize("kind", KINDS)
 def test_flat_film_bit_exact(kind):
     h0, ds, dt = CASES[kind]
     g = grid(kind, 70, 66, ds)
@@ -100,7 +109,7 @@ def test_flat_film_bit_exact(kind):
     assert res.info["newton_iters"] == 1 and res.info["e_final"] == 0.0
 
 
-@pytest.mark.parametrize("kind", ["nlc", "polymer"])
+@pytest.mark.parametrize("kind", KINDS)
 def test_trajectory_matches_oracle(orc, kind):
     """97 x 80 cells (two x tiles, one ragged), 20 backward-Euler steps, tol 1e-10: h to
     1e-10 relative, mass to 1e-12, Newton iteration counts nearly equal."""
@@ -126,7 +135,7 @@ def test_trajectory_matches_oracle(orc, kind):
     assert abs(m1 - m0) <= 1e-12 * m0
 
 
-@pytest.mark.parametrize("kind", ["nlc", "polymer"])
+@pytest.mark.parametrize("kind", KINDS)
 def test_cosine_mode_growth_rate(orc, kind):
     """A small cosine mode on the flat film grows per backward-Euler step by the discrete
     linear rate 1 / (1 + dt (f0 mu^2 - f1 mu)) (Sec. "Linear Stability Analysis"); the
@@ -152,7 +161,7 @@ def test_cosine_mode_growth_rate(orc, kind):
     assert a / (h0 * amp) == pytest.approx(gexact ** 5, rel=1e-7)
 
 
-@pytest.mark.parametrize("kind", ["nlc", "polymer"])
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("nx,ny", [(9, 7), (130, 67)])
 def test_jacobian_transpose_matches_oracle(orc, kind, nx, ny):
     ds = CASES[kind][1]
@@ -165,7 +174,7 @@ def test_jacobian_transpose_matches_oracle(orc, kind, nx, ny):
     assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("kind", ["nlc", "polymer"])
+@pytest.mark.parametrize("kind", KINDS)
 def test_adjoint_step_matches_oracle(orc, kind):
     _, ds, dt = CASES[kind]
     nx, ny = 40, 30
@@ -195,3 +204,7 @@ def test_set_model_validation():
         g.set_model_polymer(d=float("nan"))
     with pytest.raises(TFError):
         g.set_model_polymer(C=-1.0)
+    with pytest.raises(TFError):
+        g.set_model_linear(c0=0.0)
+    with pytest.raises(TFError):
+        g.set_model_linear(c1=float("inf"))

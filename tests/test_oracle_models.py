@@ -84,3 +84,35 @@ def test_discrete_growth_rate_of_new_models(orc, kind, h0, n):
         assert a / a_prev == pytest.approx(g_exact, rel=1e-7)
         a_prev = a
     assert g_exact > 1.0  # the most unstable mode grows
+
+
+@pytest.mark.parametrize("kind,h0", [("nlc", 0.5), ("polymer", 3.9)])
+def test_second_order_in_time_and_space(orc, kind, h0):
+    """Sec. "Convergence" for the new models (trapezoidal rule, eq. IC_LinearWave with
+    P = 6, q = q_m): halving dt from 1e-3 / omega_m on 32^2 cells, and tripling the grid
+    from 36 to 972 cells at one step of 1e-8 / omega_m, both converge at second order."""
+    M = getattr(orc.Model, kind)()
+    qm, wm = lsa(orc, M, h0)
+    S = orc.Scheme(theta=0.5, tol=1e-14, max_newton=5000)
+
+    def run(u, ds, dt, n):
+        for _ in range(n):
+            u, res = orc.step(M, S, u, ds, dt)
+            assert res.status == orc.OK
+        return u
+
+    u0, ds = synth.wave_film(32, 6, qm, h0)
+    sols = [run(u0, ds, 1e-3 / wm / 2 ** i, 2 ** i) for i in range(6)]
+    e = [np.sqrt(np.mean((s - sols[-1]) ** 2)) for s in sols[:-1]]
+    for i in range(2):
+        assert 1.95 <= math.log2(e[i] / e[i + 1]) <= 2.05, e
+    sols = []
+    for k in range(4):
+        u0, ds = synth.wave_film(36 * 3 ** k, 6, qm, h0)
+        sols.append(run(u0, ds, 1e-8 / wm, 1))
+    e = []
+    for k in range(3):
+        m = 3 ** (3 - k)
+        idx = m * np.arange(36 * 3 ** k) + (m - 1) // 2
+        e.append(np.sqrt(np.mean((sols[k] - sols[-1][np.ix_(idx, idx)]) ** 2)))
+    assert 1.9 <= math.log(e[1] / e[2], 3) <= 2.2, e
