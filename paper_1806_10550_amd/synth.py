@@ -66,6 +66,54 @@ def wave_film(n: int, P: float, q: float, h0: float = 1.0, ex: float = 0.1, ey: 
     return h0 * (1.0 + ex * c[None, :] + ey * c[:, None]), ds
 
 
+def perlin_noise(n: int, seed: int, alpha: float = None) -> np.ndarray:
+    """Pseudo-Perlin noise zeta of eq. PerlinNoise on n x n cells: the real part of the
+    inverse DFT of |k|^-alpha exp(2 pi i a(k)), a ~ U[-1, 1] iid per wavevector (k = 0
+    dropped), scaled so that max |zeta| = 1. alpha defaults to 200 / n."""
+    if alpha is None:
+        alpha = 200.0 / n
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1.0, 1.0, (n, n))
+    k = np.fft.fftfreq(n, d=1.0 / n)
+    m = k[None, :] ** 2 + k[:, None] ** 2
+    amp = np.zeros((n, n))
+    amp[m > 0] = m[m > 0] ** (-alpha / 2.0)
+    z = np.real(np.fft.ifft2(amp * np.exp(2j * np.pi * a)))
+    return z / np.max(np.abs(z))
+
+
+def localized_bumps(n: int, ds: float, lam_m: float, seed: int, count: int = 4, spacing: float = 8.0) -> np.ndarray:
+    """eta of eq. 3DRandomLocalTerm: a count x count array of Gaussians
+    exp(-((x - chi_i)^2 + (y - xi_j)^2) / (0.04 lam_m^2)) centred at
+    chi_i = (spacing i - spacing/2 + (spacing/2) a_i) lam_m, xi_j likewise with b_j,
+    a_i, b_j ~ U[-1, 1] (the paper's spacing is 8; the sign between the two squares is read
+    as +, a radially symmetric bump)."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1.0, 1.0, count)
+    b = rng.uniform(-1.0, 1.0, count)
+    idx = np.arange(1, count + 1)
+    chi = (spacing * idx - spacing / 2 + spacing / 2 * a) * lam_m
+    xi = (spacing * idx - spacing / 2 + spacing / 2 * b) * lam_m
+    x = (np.arange(n) + 0.5) * ds
+    gx = np.exp(-((x[None, :] - chi[:, None]) ** 2) / (0.04 * lam_m ** 2)).sum(axis=0)
+    gy = np.exp(-((x[None, :] - xi[:, None]) ** 2) / (0.04 * lam_m ** 2)).sum(axis=0)
+    return np.outer(gy, gx)
+
+
+def random_film(n: int, P: float, lam_m: float, h0: float, seed: int, eps: float = 0.01):
+    """eq. 3D_Random_IC: h0 (1 + eps |zeta|) on [0, P lam_m]^2. Returns (h, ds)."""
+    ds = P * lam_m / n
+    return h0 * (1.0 + eps * np.abs(perlin_noise(n, seed))), ds
+
+
+def mixed_film(n: int, P: float, lam_m: float, h0: float, seed: int, eps: float = 0.01):
+    """eq. 3DLocalAndRandom: h0 (1 + eps |zeta| + 10 eps eta). Returns (h, ds)."""
+    ds = P * lam_m / n
+    z = np.abs(perlin_noise(n, seed))
+    eta = localized_bumps(n, ds, lam_m, seed + 1)
+    return h0 * (1.0 + eps * z + 10.0 * eps * eta), ds
+
+
 def gaussian_depression(h: np.ndarray, ds: float, depth: float, width: float) -> np.ndarray:
     """h - depth * exp(-r^2 / width^2) about the domain centre (r measured between
     cell centres)."""
