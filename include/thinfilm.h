@@ -202,6 +202,36 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
  * (device arrays, nx*ny each). */
 tf_status tf_jacobian_apply_t(tf_grid *g, const double *u, const double *mu, double *out);
 
+/* ---- Radial Fourier transform of a film (App. "Radial Fourier Transform") ------------
+ * tf_radial_spectrum: steps 1-4 of the appendix on the GPU. h: device, n x n FP64 film
+ * (row-major, square grid of side L = n ds; 4 <= n <= 16384), read only. The magnitude of
+ * the 2D DFT of h - h0, divided by n^2, is smoothed by a periodic convolution over the
+ * integer wavenumbers (kx, ky) with the separable Gaussian weights exp(-d^2/(2 sigma^2))/Z,
+ * |d| <= ceil(4 sigma) (sigma in wavenumber units, 0 <= sigma <= 64; 0 = no smoothing),
+ * and averaged over each group of equal q_r, i.e. equal m = kx^2 + ky^2 (eq.
+ * FFT_radial_averaging), q_r = 2 pi sqrt(m) / L. Output (host arrays of `capacity`
+ * entries, in increasing q): q_out[p], s_out[p] (group mean) and count_out[p] (group size;
+ * nullable) for every nonempty group with 0 < q_r <= qmax; *npoints (host) receives the
+ * number of groups. TF_EINVAL when capacity is too small (npoints then holds the number
+ * needed) or qmax spans more than 2^26 groups. Work is enqueued on `stream` (hipStream_t,
+ * NULL = default) and the call returns after it has finished; it allocates device scratch
+ * of 16 n^2 bytes plus the smoothing window. */
+tf_status tf_radial_spectrum(const double *h, int n, double ds, double h0, double sigma, double qmax, void *stream,
+                             double *q_out, double *s_out, int *count_out, int capacity, int *npoints);
+/* tf_spectrum_maxima: steps 5-7 of the appendix (host only; all pointers host). Fits the
+ * radial data (q strictly increasing in (0, qmax], npoints >= 1) by least squares with a
+ * continuous piecewise-linear function that is 0 at q = 0, with knots at 0, at every 10th
+ * data point and at qmax (eq. PiecewiseFunction: 10 points per interval, the last interval
+ * takes the remainder); evaluates it at nfine >= 8 equispaced points of [0, qmax] (the paper
+ * uses 400) and smooths them by moving averages of half widths 3, 2, 1 (windows truncated at
+ * the ends; result in curve_out[nfine], nullable); reports the local maxima (derivative by
+ * second-order differences, a +/- sign change located by linear interpolation, negative
+ * second difference) in peak_q / peak_s (capacity entries) and their number in *npeaks.
+ * TF_EINVAL for unsorted or non-finite data, an interval without data, or too small a
+ * capacity (npeaks then holds the number found). */
+tf_status tf_spectrum_maxima(const double *q, const double *s, int npoints, double qmax, int nfine, double *curve_out,
+                             double *peak_q, double *peak_s, int capacity, int *npeaks);
+
 /* ---- Batched pentadiagonal solves on stored bands -----------------------------------
  * nlines independent systems of n unknowns (n >= 2). Layout position-major: element
  * (position p, line l) at p*nlines + l. bands: 5 device arrays of n*nlines doubles back

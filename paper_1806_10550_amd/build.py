@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libthinfilm.so")
-SOURCES = ["tf_kernels.hip", "tf_api.hip", "tf_ensemble.hip", "tf_adjoint.hip"]
+SOURCES = ["tf_kernels.hip", "tf_api.hip", "tf_ensemble.hip", "tf_adjoint.hip", "tf_spectrum.hip"]
+LIBS = ["-lhipfft"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -18,7 +19,7 @@ FLAGS = [
 
 def build(verbose: bool = False, extra=None) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = ["hipcc"] + FLAGS + (extra or []) + srcs + ["-o", LIB + ".tmp"]
+    cmd = ["hipcc"] + FLAGS + (extra or []) + srcs + LIBS + ["-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -7,6 +7,7 @@ missing this module raises instead of falling back to anything else.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass
 
@@ -59,6 +60,8 @@ def lib():
         L.tf_destroy.argtypes = [P]
         L.tf_set_model.argtypes = [P, D, D, D, D]
         L.tf_set_model_linear.argtypes = [P, D, D]
+        L.tf_radial_spectrum.argtypes = [P, C.c_int, D, D, D, D, P, P, P, P, C.c_int, P]
+        L.tf_spectrum_maxima.argtypes = [P, P, C.c_int, D, C.c_int, P, P, P, C.c_int, P]
         L.tf_model_coeffs.argtypes = [P, P, C.c_int, P]
         L.tf_set_model_nlc.argtypes = [P, D, D, D, D, D, D]
         L.tf_set_model_polymer.argtypes = [P, D, D, D, D, D]
@@ -344,6 +347,45 @@ def penta_solve(bands, rhs, x, transposed=False, variant="auto", stream=None):
     _check(lib().tf_penta_solve(int(nl), int(n), _ptr(bands), _ptr(rhs), _ptr(x), int(bool(transposed)),
                                 VARIANTS[variant], _stream_ptr(stream)))
     return x
+
+
+def radial_spectrum(h, ds: float, h0: float, sigma: float = 1.0, qmax: float = None, stream=None):
+    """Steps 1-4 of the radial Fourier transform (tf_radial_spectrum) of a square (n, n)
+    float64 CUDA film: returns numpy arrays (q, mean, count) over the groups of equal
+    |k|^2 with 0 < q <= qmax (default: the whole spectrum)."""
+    import numpy as np
+    n = int(h.shape[0])
+    if tuple(h.shape) != (n, n):
+        raise ValueError("the film must be square")
+    L = n * ds
+    if qmax is None:
+        qmax = 2 * math.pi * math.sqrt(2.0) * (n // 2) / L
+    cap = int(min((qmax * L / (2 * math.pi)) ** 2 * (1 + 1e-12), 2.0 * (n // 2) ** 2)) + 2
+    cap = min(cap, (1 << 26) + 2)
+    q = np.empty(cap)
+    v = np.empty(cap)
+    c = np.empty(cap, dtype=np.int32)
+    npts = C.c_int(0)
+    _check(lib().tf_radial_spectrum(_ptr(h), n, float(ds), float(h0), float(sigma), float(qmax), _stream_ptr(stream),
+                                    q.ctypes.data, v.ctypes.data, c.ctypes.data, cap, C.byref(npts)))
+    k = npts.value
+    return q[:k].copy(), v[:k].copy(), c[:k].copy()
+
+
+def spectrum_maxima(q, s, qmax: float, nfine: int = 400, capacity: int = 64):
+    """Steps 5-7 (tf_spectrum_maxima): returns (x, smoothed curve, [(q, value) of each
+    local maximum])."""
+    import numpy as np
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    curve = np.empty(nfine)
+    pq = np.empty(capacity)
+    ps = np.empty(capacity)
+    npk = C.c_int(0)
+    _check(lib().tf_spectrum_maxima(q.ctypes.data, s.ctypes.data, len(q), float(qmax), int(nfine), curve.ctypes.data,
+                                    pq.ctypes.data, ps.ctypes.data, int(capacity), C.byref(npk)))
+    x = np.linspace(0.0, qmax, nfine)
+    return x, curve, [(float(pq[i]), float(ps[i])) for i in range(npk.value)]
 
 
 def autotune(length: int, batch: int, cache_path: str | None = None, transposed: bool = False) -> str:
