@@ -13,6 +13,7 @@ rate on the host (a bounded sample, see cpu_baseline.sample).
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -204,15 +205,59 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_spectrum(args):
+    """Radial Fourier transform (steps 1-4 on the GPU, 5-7 in the library on the host) of an
+    NLC film at the paper's largest grid: I = 4000, P = 40 wavelengths at H0 = 0.5,
+    pseudo-Perlin noise (eq. 3D_Random_IC, seed 7); sigma = 1, q <= 5 q_m."""
+    import torch
+
+    from paper_1806_10550_amd import synth
+    from paper_1806_10550_amd.lib import radial_spectrum, spectrum_maxima
+
+    n, P, h0, qm = 4000, 40, 0.5, 1.4821222565068524
+    lam = 2 * math.pi / qm
+    h_np, ds = synth.random_film(n, P, lam, h0, seed=7)
+    h = torch.from_numpy(h_np).to("cuda:0")
+    qmax = 5 * qm
+    for _ in range(args.warmup):
+        radial_spectrum(h, ds, h0, 1.0, qmax)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        q, v, _ = radial_spectrum(h, ds, h0, 1.0, qmax)
+        _, _, peaks = spectrum_maxima(q, v, qmax)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    algo = 8.0 * n * n  # the film must be read once
+    out = {"metric": "radial Fourier spectra per second (App. Radial Fourier Transform)", "value": 1.0 / t,
+           "unit": "spectra/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t,
+           "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"NLC film {n}x{n}, P={P} wavelengths at H0={h0}, pseudo-Perlin noise seed 7, "
+                                  f"sigma=1, q<=5q_m"},
+           "roofline": {"bound": "hbm", "kernel": "whole call (FFT + smoothing + group sums + readback)",
+                        "achieved": algo / t / 1e9, "peak": 8000.0, "unit": "GB/s", "frac": algo / t / 8e12,
+                        "traffic": None},
+           "groups": int(len(q)), "peaks": len(peaks)}
+    if not args.no_cpu_baseline:
+        from oracle import radial as R
+        t1 = time.perf_counter()
+        R.dominant_wavenumbers(h_np, h0, ds, 1.0, qmax)
+        tc = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": 1.0 / tc, "unit": "spectra/s", "cores": 1, "kind": "oracle",
+                               "sample": "one full spectrum of the same film (NumPy FFT, one thread)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="large8192")
-    ap.add_argument("--workload", default="single", choices=["single", "ensemble", "adjoint"],
+    ap.add_argument("--workload", default="single", choices=["single", "ensemble", "adjoint", "spectrum"],
                     help="single: the 8192^2 film (default); ensemble: 256 ragged films; "
-                         "adjoint: 512^2 gradient by the checkpointed adjoint")
+                         "adjoint: 512^2 gradient by the checkpointed adjoint; "
+                         "spectrum: radial Fourier transform of a 4000^2 film")
     ap.add_argument("--films", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -242,6 +287,9 @@ def main():
         return
     if args.workload == "adjoint":
         bench_adjoint(args)
+        return
+    if args.workload == "spectrum":
+        bench_spectrum(args)
         return
 
     import torch

@@ -214,10 +214,14 @@ tf_status tf_jacobian_apply_t(tf_grid *g, const double *u, const double *mu, dou
  * nullable) for every nonempty group with 0 < q_r <= qmax; *npoints (host) receives the
  * number of groups. TF_EINVAL when capacity is too small (npoints then holds the number
  * needed) or qmax spans more than 2^26 groups. Work is enqueued on `stream` (hipStream_t,
- * NULL = default) and the call returns after it has finished; it allocates device scratch
- * of 16 n^2 bytes plus the smoothing window. */
+ * NULL = default) and the call returns after it has finished. The FFT plan and device scratch
+ * (8 n (n + 2) bytes plus the smoothing window and group sums) are kept per (device, n) for
+ * later calls until tf_spectrum_release; calls are serialised by a lock. */
 tf_status tf_radial_spectrum(const double *h, int n, double ds, double h0, double sigma, double qmax, void *stream,
                              double *q_out, double *s_out, int *count_out, int capacity, int *npoints);
+/* Frees the plans and scratch kept by tf_radial_spectrum on every device (waits for each
+ * device first). Always TF_OK. */
+tf_status tf_spectrum_release(void);
 /* tf_spectrum_maxima: steps 5-7 of the appendix (host only; all pointers host). Fits the
  * radial data (q strictly increasing in (0, qmax], npoints >= 1) by least squares with a
  * continuous piecewise-linear function that is 0 at q = 0, with knots at 0, at every 10th

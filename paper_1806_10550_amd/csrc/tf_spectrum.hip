@@ -1,8 +1,9 @@
 // Radial Fourier spectrum of a film (App. "Radial Fourier Transform"; see include/thinfilm.h,
 // tf_radial_spectrum and tf_spectrum_maxima).
 //
-// Device part (steps 1-4): the film minus H0 is transformed by a 2D complex FFT (hipFFT); the
-// magnitudes are gathered into a window of the wavenumber plane that covers the disk
+// Device part (steps 1-4): the film minus H0 is transformed by an in-place 2D real-to-complex
+// FFT (hipFFT; half spectrum, the other half by conjugate symmetry); the magnitudes are
+// gathered into a window of the wavenumber plane that covers the disk
 // |k|^2 <= M plus the Gaussian's reach (indices taken modulo n, so the smoothing is the
 // periodic convolution over the whole plane); two separable passes smooth the window; one
 // thread per wavevector of the disk adds its smoothed value into the sum of its group
@@ -25,16 +26,20 @@
 
 namespace tf {
 
-__global__ void __launch_bounds__(256) k_spec_load(const double *__restrict__ h, double h0, size_t N,
-                                                   hipfftDoubleComplex *__restrict__ z)
+// buf[j * pitch + i] = h[j * n + i] - h0: the film minus H0 in the padded row layout of an
+// in-place real-to-complex transform (pitch = 2 (n/2 + 1) doubles).
+__global__ void __launch_bounds__(256) k_spec_load(const double *__restrict__ h, double h0, int n, int pitch,
+                                                   double *__restrict__ buf)
 {
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
-    z[k].x = h[k] - h0;
-    z[k].y = 0.0;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= n) return;
+    buf[(size_t)j * pitch + i] = h[(size_t)j * n + i] - h0;
 }
 
-// A[(wy + E) * W + (wx + E)] = |F(wy mod n, wx mod n)| / n^2 for wx, wy in [-E, E].
+// A[(wy + E) * W + (wx + E)] = |F(wx mod n, wy mod n)| / n^2 for wx, wy in [-E, E], from the
+// half spectrum F[iy][ix], ix <= n/2, of the real transform: the other half follows from
+// F(-k) = conj F(k).
 __global__ void __launch_bounds__(256) k_spec_window(const hipfftDoubleComplex *__restrict__ F, int n, int E,
                                                      double inv_n2, double *__restrict__ A)
 {
@@ -42,8 +47,12 @@ __global__ void __launch_bounds__(256) k_spec_window(const hipfftDoubleComplex *
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= W * W) return;
     const int wx = t % W - E, wy = t / W - E;
-    const int ix = ((wx % n) + n) % n, iy = ((wy % n) + n) % n;
-    const hipfftDoubleComplex c = F[(size_t)iy * n + ix];
+    int ix = ((wx % n) + n) % n, iy = ((wy % n) + n) % n;
+    if (ix > n / 2) {
+        ix = n - ix;
+        iy = (n - iy) % n;
+    }
+    const hipfftDoubleComplex c = F[(size_t)iy * (n / 2 + 1) + ix];
     A[t] = sqrt(c.x * c.x + c.y * c.y) * inv_n2;
 }
 
@@ -96,40 +105,73 @@ tf_status sfail(tf_status s, const std::string &msg)
     return s;
 }
 
-struct PlanKey {
-    int device, n;
-    bool operator<(const PlanKey &o) const { return device != o.device ? device < o.device : n < o.n; }
+// Plan and scratch of one (device, n), kept until tf_spectrum_release: the padded real /
+// half-complex buffer of the in-place transform and the small window and group arrays
+// (grown on demand).
+struct SpecWork {
+    hipfftHandle plan = 0;
+    bool has_plan = false;
+    double *buf = nullptr;
+    double *small = nullptr; // A | B | C | weights | sums, doubles
+    int *cnt = nullptr;
+    size_t small_cap = 0, cnt_cap = 0;
 };
-std::mutex g_plan_mu;
-std::map<PlanKey, hipfftHandle> g_plans;
+struct WorkKey {
+    int device, n;
+    bool operator<(const WorkKey &o) const { return device != o.device ? device < o.device : n < o.n; }
+};
+std::mutex g_spec_mu;
+std::map<WorkKey, SpecWork> g_spec;
 
-// One cached plan per (device, n); the caller holds g_plan_mu while using it.
-bool get_plan(int n, hipfftHandle *out)
+void free_work(SpecWork &w)
 {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return false;
-    const PlanKey key{dev, n};
-    auto it = g_plans.find(key);
-    if (it != g_plans.end()) {
-        *out = it->second;
-        return true;
-    }
-    hipfftHandle p;
-    if (hipfftPlan2d(&p, n, n, HIPFFT_Z2Z) != HIPFFT_SUCCESS) return false;
-    g_plans[key] = p;
-    *out = p;
-    return true;
+    if (w.has_plan) (void)hipfftDestroy(w.plan);
+    if (w.buf) (void)hipFree(w.buf);
+    if (w.small) (void)hipFree(w.small);
+    if (w.cnt) (void)hipFree(w.cnt);
+    w = SpecWork{};
 }
 
-struct DevBuf {
-    void *p = nullptr;
-    ~DevBuf()
-    {
-        if (p) (void)hipFree(p);
+// Called with g_spec_mu held.
+tf_status get_work(int n, size_t small_doubles, size_t groups, SpecWork **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return sfail(TF_EDEVICE, "hipGetDevice failed");
+    SpecWork &w = g_spec[WorkKey{dev, n}];
+    if (!w.has_plan) {
+        if (hipfftPlan2d(&w.plan, n, n, HIPFFT_D2Z) != HIPFFT_SUCCESS) return sfail(TF_EDEVICE, "hipfftPlan2d failed");
+        w.has_plan = true;
     }
-};
+    if (w.buf == nullptr
+        && hipMalloc(&w.buf, (size_t)n * (n / 2 + 1) * sizeof(hipfftDoubleComplex)) != hipSuccess) {
+        w.buf = nullptr;
+        return sfail(TF_ENOMEM, "spectrum buffer allocation failed");
+    }
+    if (w.small_cap < small_doubles) {
+        if (w.small) (void)hipFree(w.small);
+        w.small = nullptr;
+        w.small_cap = 0;
+        if (hipMalloc(&w.small, small_doubles * sizeof(double)) != hipSuccess) {
+            w.small = nullptr;
+            return sfail(TF_ENOMEM, "spectrum scratch allocation failed");
+        }
+        w.small_cap = small_doubles;
+    }
+    if (w.cnt_cap < groups) {
+        if (w.cnt) (void)hipFree(w.cnt);
+        w.cnt = nullptr;
+        w.cnt_cap = 0;
+        if (hipMalloc(&w.cnt, groups * sizeof(int)) != hipSuccess) {
+            w.cnt = nullptr;
+            return sfail(TF_ENOMEM, "spectrum scratch allocation failed");
+        }
+        w.cnt_cap = groups;
+    }
+    *out = &w;
+    return TF_OK;
+}
 
-// Waits for the stream on every exit, before the scratch buffers (declared earlier) are freed.
+// Waits for the stream on every exit, so that no work of a failed call is left queued.
 struct StreamDrain {
     hipStream_t s;
     ~StreamDrain() { (void)hipStreamSynchronize(s); }
@@ -167,44 +209,36 @@ tf_status tf_radial_spectrum(const double *h, int n, double ds, double h0, doubl
         for (double &v : w) v /= z;
     }
     hipStream_t s = (hipStream_t)stream;
-    const size_t N = (size_t)n * n;
-    DevBuf z, A, B, C, wd, sum, cnt;
+    // small scratch: A (W x W) | B (Wr x W) | C (Wr x Wr) | weights | group sums
+    const size_t oA = 0, oB = oA + (size_t)W * W, oC = oB + (size_t)W * Wr, oW = oC + (size_t)Wr * Wr,
+                 oS = oW + w.size(), small = oS + (size_t)(M + 1);
+    std::lock_guard<std::mutex> lk(g_spec_mu);
+    SpecWork *wk;
+    tf_status st = get_work(n, small, (size_t)(M + 1), &wk);
+    if (st != TF_OK) return st;
     StreamDrain drain{s};
-    if (hipMalloc(&z.p, N * sizeof(hipfftDoubleComplex)) != hipSuccess
-        || hipMalloc(&A.p, (size_t)W * W * sizeof(double)) != hipSuccess
-        || hipMalloc(&B.p, (size_t)W * Wr * sizeof(double)) != hipSuccess
-        || hipMalloc(&C.p, (size_t)Wr * Wr * sizeof(double)) != hipSuccess
-        || hipMalloc(&wd.p, w.size() * sizeof(double)) != hipSuccess
-        || hipMalloc(&sum.p, (size_t)(M + 1) * sizeof(double)) != hipSuccess
-        || hipMalloc(&cnt.p, (size_t)(M + 1) * sizeof(int)) != hipSuccess)
-        return sfail(TF_ENOMEM, "spectrum scratch allocation failed");
-    auto *Z = (hipfftDoubleComplex *)z.p;
-    tf::k_spec_load<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(h, h0, N, Z);
+    double *A = wk->small + oA, *B = wk->small + oB, *C = wk->small + oC, *wd = wk->small + oW,
+           *sum = wk->small + oS;
+    const int pitch = 2 * (n / 2 + 1);
+    tf::k_spec_load<<<dim3((n + 255) / 256, n), 256, 0, s>>>(h, h0, n, pitch, wk->buf);
     if (hipGetLastError() != hipSuccess) return sfail(TF_EDEVICE, "spectrum load launch failed");
-    {
-        std::lock_guard<std::mutex> lk(g_plan_mu);
-        hipfftHandle plan;
-        if (!get_plan(n, &plan)) return sfail(TF_EDEVICE, "hipfftPlan2d failed");
-        if (hipfftSetStream(plan, s) != HIPFFT_SUCCESS || hipfftExecZ2Z(plan, Z, Z, HIPFFT_FORWARD) != HIPFFT_SUCCESS)
-            return sfail(TF_EDEVICE, "hipfftExecZ2Z failed");
-    }
-    if (hipMemcpyAsync(wd.p, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess
-        || hipMemsetAsync(sum.p, 0, (size_t)(M + 1) * sizeof(double), s) != hipSuccess
-        || hipMemsetAsync(cnt.p, 0, (size_t)(M + 1) * sizeof(int), s) != hipSuccess)
+    auto *F = (hipfftDoubleComplex *)wk->buf;
+    if (hipfftSetStream(wk->plan, s) != HIPFFT_SUCCESS || hipfftExecD2Z(wk->plan, wk->buf, F) != HIPFFT_SUCCESS)
+        return sfail(TF_EDEVICE, "hipfftExecD2Z failed");
+    if (hipMemcpyAsync(wd, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess
+        || hipMemsetAsync(sum, 0, (size_t)(M + 1) * sizeof(double), s) != hipSuccess
+        || hipMemsetAsync(wk->cnt, 0, (size_t)(M + 1) * sizeof(int), s) != hipSuccess)
         return sfail(TF_EDEVICE, "spectrum scratch setup failed");
     const double inv_n2 = 1.0 / ((double)n * (double)n);
-    tf::k_spec_window<<<(W * W + 255) / 256, 256, 0, s>>>(Z, n, E, inv_n2, (double *)A.p);
-    tf::k_spec_smooth<0><<<(Wr * W + 255) / 256, 256, 0, s>>>((const double *)A.p, W, W, (const double *)wd.p, r,
-                                                              (double *)B.p);
-    tf::k_spec_smooth<1><<<(Wr * Wr + 255) / 256, 256, 0, s>>>((const double *)B.p, Wr, W, (const double *)wd.p, r,
-                                                               (double *)C.p);
-    tf::k_spec_radial<<<(Wr * Wr + 255) / 256, 256, 0, s>>>((const double *)C.p, R, n, M, (double *)sum.p,
-                                                            (int *)cnt.p);
+    tf::k_spec_window<<<(W * W + 255) / 256, 256, 0, s>>>(F, n, E, inv_n2, A);
+    tf::k_spec_smooth<0><<<(Wr * W + 255) / 256, 256, 0, s>>>(A, W, W, wd, r, B);
+    tf::k_spec_smooth<1><<<(Wr * Wr + 255) / 256, 256, 0, s>>>(B, Wr, W, wd, r, C);
+    tf::k_spec_radial<<<(Wr * Wr + 255) / 256, 256, 0, s>>>(C, R, n, M, sum, wk->cnt);
     if (hipGetLastError() != hipSuccess) return sfail(TF_EDEVICE, "spectrum kernel launch failed");
     std::vector<double> hs(M + 1);
     std::vector<int> hc(M + 1);
-    if (hipMemcpyAsync(hs.data(), sum.p, (M + 1) * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess
-        || hipMemcpyAsync(hc.data(), cnt.p, (M + 1) * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess
+    if (hipMemcpyAsync(hs.data(), sum, (M + 1) * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess
+        || hipMemcpyAsync(hc.data(), wk->cnt, (M + 1) * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess
         || hipStreamSynchronize(s) != hipSuccess)
         return sfail(TF_EDEVICE, "spectrum readback failed");
     int np = 0;
@@ -222,6 +256,21 @@ tf_status tf_radial_spectrum(const double *h, int n, double ds, double h0, doubl
     *npoints = np;
     if (np > capacity || (np > 0 && (q_out == nullptr || s_out == nullptr)))
         return sfail(TF_EINVAL, "output capacity too small (npoints holds the number needed)");
+    return TF_OK;
+}
+
+tf_status tf_spectrum_release(void)
+{
+    std::lock_guard<std::mutex> lk(g_spec_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : g_spec) {
+        (void)hipSetDevice(kv.first.device);
+        (void)hipDeviceSynchronize();
+        free_work(kv.second);
+    }
+    g_spec.clear();
+    (void)hipSetDevice(cur);
     return TF_OK;
 }
 

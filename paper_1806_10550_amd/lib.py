@@ -372,6 +372,11 @@ def radial_spectrum(h, ds: float, h0: float, sigma: float = 1.0, qmax: float = N
     return q[:k].copy(), v[:k].copy(), c[:k].copy()
 
 
+def spectrum_release() -> None:
+    """Free the FFT plans and scratch kept by radial_spectrum (tf_spectrum_release)."""
+    _check(lib().tf_spectrum_release())
+
+
 def spectrum_maxima(q, s, qmax: float, nfine: int = 400, capacity: int = 64):
     """Steps 5-7 (tf_spectrum_maxima): returns (x, smoothed curve, [(q, value) of each
     local maximum])."""

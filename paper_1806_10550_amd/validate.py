@@ -48,10 +48,11 @@ def make_grid(kind, n, ds, **scheme):
     return g
 
 
-def lsa_params(kind):
-    """(H0, f0(H0), f1(H0), q_m, omega_m): q_m^2 = f1 / (2 f0), omega_m = f1^2 / (4 f0)."""
+def lsa_params(kind, h0=None):
+    """(H0, f0(H0), f1(H0), q_m, omega_m): q_m^2 = f1 / (2 f0), omega_m = f1^2 / (4 f0);
+    H0 defaults to the model's thickness in Sec. "Validation"."""
     torch = _torch()
-    h0 = MODELS[kind]
+    h0 = MODELS[kind] if h0 is None else h0
     g = make_grid(kind, 4, 1.0)
     out = torch.empty((1, 4), dtype=torch.float64, device="cuda:0")
     g.model_coeffs(torch.full((1,), h0, dtype=torch.float64, device="cuda:0"), out)

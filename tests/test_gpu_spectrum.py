@@ -70,6 +70,17 @@ def test_full_size_and_dominant_wavenumbers():
     assert abs(top[0] - QM) <= 0.05 * QM
 
 
+def test_release_and_reuse():
+    """Cached plans and scratch are freed and rebuilt; results are unchanged."""
+    from paper_1806_10550_amd.lib import spectrum_release
+    h, ds = synth.random_film(96, 4, LAM, H0, seed=3)
+    a = radial_spectrum(torch.from_numpy(h).to(DEV), ds, H0, 1.0, 5 * QM)
+    spectrum_release()
+    b = radial_spectrum(torch.from_numpy(h).to(DEV), ds, H0, 1.0, 5 * QM)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+    assert np.max(np.abs(a[1] - b[1])) <= 1e-14 * np.max(a[1])
+
+
 def test_argument_errors():
     h = torch.ones((8, 8), dtype=torch.float64, device=DEV)
     with pytest.raises(TFError):
