@@ -477,6 +477,7 @@ tf_status tf_set_model_nlc(tf_grid *g, double C, double K, double N, double beta
     M.N = N;
     M.beta2 = beta * beta;
     M.w = w;
+    M.iw = 1.0 / w;
     M.b = b;
     g->M = M;
     g->model_set = true;

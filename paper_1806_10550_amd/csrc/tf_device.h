@@ -27,29 +27,61 @@ __device__ __forceinline__ double ipow(double r, double h, int k)
     return acc;
 }
 
+// x^k for 0 <= k < 16 by binary powering with a fixed number of steps (no data-dependent
+// loop, so the sweep kernels keep their registers).
+__device__ __forceinline__ double pow16(double x, int k)
+{
+    double acc = 1.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        acc = (k & 1) ? acc * x : acc;
+        x *= x;
+        k >>= 1;
+    }
+    return acc;
+}
+
 // Pi'(h) and Pi''(h) of the NLC and polymer models (see Model), r = 1/h. NLC, with
 // q = m(h)/h = g(h) s(h), s = h / (h^2 + beta^2):
 //   Pi'  = K(-3 b^3 h^-4 + 2 b^2 h^-3) + N q q',
 //   Pi'' = K(12 b^3 h^-5 - 6 b^2 h^-4) + N (q'^2 + q q'').
-__device__ __forceinline__ void disjoining_derivs(const Model &M, double h, double r, double &pip, double &pipp)
+// g = (1 + tanh z)/2 = 1/(1 + e), e = exp(-2z), z = (h - 2b)/w, so that
+//   tanh z = g (1 - e),  1 - tanh^2 z = 4 e g^2,  g' = (1 - tanh^2 z)/(2w),
+//   g'' = -(1 - tanh^2 z) tanh z / w^2
+// (one exponential and one reciprocal; every factor stays accurate when g is near 0 or 1).
+__device__ __forceinline__ void nlc_derivs(const Model &M, double h, double r, double &pip, double &pipp)
 {
     const double r2 = r * r, r4 = r2 * r2, r5 = r4 * r;
-    if (M.kind == MODEL_NLC) {
-        const double z = (h - 2.0 * M.b) / M.w;
-        const double th = tanh(z), s2 = 1.0 - th * th;
-        const double g = 0.5 * (1.0 + th), gp = 0.5 * s2 / M.w, gpp = -s2 * th / (M.w * M.w);
+    {
+        const double mz2 = fmin(-2.0 * (h - 2.0 * M.b) * M.iw, 700.0);
+        const double e = exp(mz2);
+        const double g = rcp(1.0 + e);
+        const double s2 = 4.0 * e * (g * g), th = g * (1.0 - e);
+        const double gp = 0.5 * s2 * M.iw, gpp = -s2 * th * (M.iw * M.iw);
         const double rd = rcp(h * h + M.beta2);
         const double sv = h * rd, sp = (M.beta2 - h * h) * rd * rd, spp = 2.0 * h * (h * h - 3.0 * M.beta2) * rd * rd * rd;
         const double q = g * sv, qp = gp * sv + g * sp, qpp = gpp * sv + 2.0 * gp * sp + g * spp;
         const double b2 = M.b * M.b, b3 = b2 * M.b;
         pip = M.K * (-3.0 * b3 * r4 + 2.0 * b2 * r2 * r) + M.N * q * qp;
         pipp = M.K * (12.0 * b3 * r5 - 6.0 * b2 * r4) + M.N * (qp * qp + q * qpp);
-    } else {
+    }
+}
+
+__device__ __forceinline__ void polymer_derivs(const Model &M, double h, double r, double &pip, double &pipp)
+{
+    const double r2 = r * r, r4 = r2 * r2, r5 = r4 * r;
+    {
         const double e = rcp(h + M.d), e2 = e * e, e4 = e2 * e2;
         const double r10 = r5 * r5;
         pip = -9.0 * M.C8 * r10 + 3.0 * M.a2 * r4 - 3.0 * M.c2 * e4;
         pipp = 90.0 * M.C8 * r10 * r - 12.0 * M.a2 * r5 + 12.0 * M.c2 * e4 * e;
     }
+}
+
+__device__ __forceinline__ void disjoining_derivs(const Model &M, double h, double r, double &pip, double &pipp)
+{
+    if (M.kind == MODEL_NLC) nlc_derivs(M, h, r, pip, pipp);
+    else polymer_derivs(M, h, r, pip, pipp);
 }
 
 // f0 = cap h^3, f0' = 3 cap h^2, f1 = h^3 Pi'(h), f1' = 3 h^2 Pi' + h^3 Pi'' (see Model);

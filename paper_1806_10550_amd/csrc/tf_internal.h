@@ -51,6 +51,9 @@ __host__ __device__ inline int seg_start(int q, int n)
 // MODEL_POLYMER: Pi = -psi', psi = Cst h^-8 - Aox/(12 pi h^2) + (Aox - Asi)/(12 pi (h+d)^2)
 //   (eq. DisjPressPolymer), stored as Pi = C8 h^-9 - a2 h^-3 + c2 (h+d)^-3.
 enum ModelKind { MODEL_POWER = 0, MODEL_LINEAR = 1, MODEL_NLC = 2, MODEL_POLYMER = 3 };
+// Model form compiled into the sweep kernels (one instantiation each): the power law with
+// n = 3, m = 2, any other power law, the linear model, NLC, polymer.
+enum KernelModel { KM_P32 = 0, KM_POWER = 1, KM_LINEAR = 2, KM_NLC = 3, KM_POLYMER = 4 };
 struct Model {
     double kappa, b;
     int n, m;
@@ -58,7 +61,7 @@ struct Model {
     bool p32; // power law with n == 3 && m == 2: f1 = Cm - Cn r, f1' = Dn r^2
     int kind;
     double cap;                // C in f0 = C h^3 (c0 of the linear model)
-    double K, N, beta2, w;     // NLC (with b)
+    double K, N, beta2, w, iw; // NLC (with b); iw = 1/w
     double C8, a2, c2, d;      // polymer
 };
 

@@ -69,7 +69,7 @@ struct CellS {
     double u, lap, f0, f1, g0, g1;
 };
 
-template <int DIR, bool P32>
+template <int DIR, int KM>
 __device__ __forceinline__ CellS cell_s(const double *sU, const PassParams &p, int l, int q)
 {
     CellS c;
@@ -83,7 +83,7 @@ __device__ __forceinline__ CellS cell_s(const double *sU, const PassParams &p, i
         yp = uat<DIR>(sU, l + 1, q); ym = uat<DIR>(sU, l - 1, q);
     }
     c.lap = __builtin_fma(-4.0, c.u, (xp + xm) + (yp + ym));
-    if (!P32 && p.M.kind == MODEL_LINEAR) {
+    if constexpr (KM == KM_LINEAR) {
         c.f0 = p.f0s;
         c.g0 = 0.0;
         c.f1 = p.M.Cm;
@@ -94,16 +94,20 @@ __device__ __forceinline__ CellS cell_s(const double *sU, const PassParams &p, i
     const double u2 = c.u * c.u;
     c.f0 = (u2 * c.u) * p.f0s;
     c.g0 = p.K0 * u2;
-    if (P32) {
+    if constexpr (KM == KM_P32) {
         c.f1 = __builtin_fma(-p.M.Cn, r, p.M.Cm);
         c.g1 = p.K1 * (r * r);
-    } else if (p.M.kind == MODEL_POWER) {
+    } else if constexpr (KM == KM_POWER) {
+        // r^(m-1), r^(n-1) by fixed-step powering (0 <= m-1 < n-1 <= 15), then one
+        // multiplication by h = 1/r for r^(m-2), r^(n-2)
         const Model &M = p.M;
-        c.f1 = M.Cm * ipow(r, c.u, M.m - 2) - M.Cn * ipow(r, c.u, M.n - 2);
-        c.g1 = p.ka * (M.Dn * ipow(r, c.u, M.n - 1) - M.Dm * ipow(r, c.u, M.m - 1));
+        const double pm1 = pow16(r, M.m - 1), pn1 = pm1 * pow16(r, M.n - M.m);
+        c.f1 = M.Cm * (pm1 * c.u) - M.Cn * (pn1 * c.u);
+        c.g1 = p.ka * (M.Dn * pn1 - M.Dm * pm1);
     } else {
         double pip, pipp;
-        disjoining_derivs(p.M, c.u, r, pip, pipp);
+        if constexpr (KM == KM_NLC) nlc_derivs(p.M, c.u, r, pip, pipp);
+        else polymer_derivs(p.M, c.u, r, pip, pipp);
         c.f1 = (u2 * c.u) * pip;
         c.g1 = p.ka * (3.0 * u2 * pip + (u2 * c.u) * pipp);
     }
@@ -140,7 +144,7 @@ __device__ __forceinline__ FaceS face_s(const CellS &L, const CellS &R, bool int
 // bands of I + c J, and runs the LU step with the sub-segment's outer unknowns kept
 // symbolic. FAST: interior tile with 16 positions per wave, no domain boundary inside
 // (no folded ghost columns, no zero-flux faces, no per-lane boundary selects).
-template <int DIR, bool SOLVE, bool P32, bool FAST>
+template <int DIR, bool SOLVE, int KM, bool FAST>
 __device__ __forceinline__ void sweep(const double *sU, double *sB, const double *bcol, const PassParams &p,
                                       int lane, int ps, int len, int pbase, int Np, int gl, int Nl, bool owned, double *fa,
                                       double *fb, double *fz, double *fph, double *fps, Rel &mine,
@@ -150,8 +154,8 @@ __device__ __forceinline__ void sweep(const double *sU, double *sB, const double
     // x relations pass: w read straight from global memory (each lane walks its row)
     constexpr bool WG = DIR == 1 && !SOLVE;
     {
-        const CellS cm = cell_s<DIR, P32>(sU, p, lane, ps - 1);
-        CellS c0 = cell_s<DIR, P32>(sU, p, lane, ps);
+        const CellS cm = cell_s<DIR, KM>(sU, p, lane, ps - 1);
+        CellS c0 = cell_s<DIR, KM>(sU, p, lane, ps);
         FaceS fm = face_s<DIR == 0>(cm, c0, FAST || pbase + ps > 0, ka);
         double al1 = 0.0, be1 = 0.0, al2 = 0.0, be2 = 0.0;
         // rows s-2 and s-1 stand for the outer unknowns l1 and l2
@@ -166,7 +170,7 @@ __device__ __forceinline__ void sweep(const double *sU, double *sB, const double
             if (FAST || k < len) {
                 const int lp = ps + k;
                 const int gp = pbase + lp;          // wave-uniform
-                const CellS cp = cell_s<DIR, P32>(sU, p, lane, lp + 1);
+                const CellS cp = cell_s<DIR, KM>(sU, p, lane, lp + 1);
                 const FaceS fp = face_s<DIR == 0>(c0, cp, FAST || gp < Np - 1, ka);
                 double rhs;
                 if (DIR == 0) {
@@ -307,7 +311,7 @@ __device__ __forceinline__ void stage_tile(const PassParams &p, double *sU, doub
         if (xoff[k] >= 0) sU[xoff[k]] = vx[k];
 }
 
-template <int DIR, bool SOLVE, bool P32>
+template <int DIR, bool SOLVE, int KM>
 __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
 {
     // LDS: the u tile, then (solve passes) the tile of the second input (b^n, w) which
@@ -371,10 +375,10 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
                                   : p.in2 + (size_t)min(y0 + lane, ny - 1) * nx + (x0 + ps);
     if (len > 0) {
         if (fast)
-            sweep<DIR, SOLVE, P32, true>(sU, sB, bcol, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph,
+            sweep<DIR, SOLVE, KM, true>(sU, sB, bcol, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph,
                                          fps, mine, rmax, flags);
         else
-            sweep<DIR, SOLVE, P32, false>(sU, sB, bcol, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph,
+            sweep<DIR, SOLVE, KM, false>(sU, sB, bcol, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph,
                                           fps, mine, rmax, flags);
     }
 
@@ -491,24 +495,34 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
 #define TF_PASS_ATTR                                                                         \
     __launch_bounds__(BLOCK)                                                                 \
     __attribute__((amdgpu_waves_per_eu(TF_PASS_WPE, TF_PASS_WPE)))
-// waves per SIMD the pass is compiled for: the relations passes of the n = 3, m = 2
-// model fit in 128 VGPRs (their LDS footprint admits 4 workgroups per CU); the solve
-// passes hold their factors in registers
-#define TF_PASS_WPE (SOLVE ? K3_WAVES_PER_EU : (!P32 ? 2 : (DIR == 0 ? K1Y_WAVES_PER_EU : K1X_WAVES_PER_EU)))
+// waves per SIMD each pass is compiled for (pass_waves_per_eu): the relations passes of the
+// n = 3, m = 2 model fit in 128 VGPRs (their LDS footprint admits 4 workgroups per CU); the
+// solve passes hold their factors in registers
+#define TF_PASS_WPE pass_waves_per_eu(DIR, SOLVE, KM)
+// (NLC and polymer chosen by timing at 8192^2: they need more registers per wave, the y
+// relations pass of NLC the most; the linear model fits the n = 3, m = 2 budget, the
+// general power law 168 VGPRs)
+constexpr int pass_waves_per_eu(int dir, bool solve, int km)
+{
+    return solve ? K3_WAVES_PER_EU
+                 : (km == KM_P32 || km == KM_LINEAR) ? (dir == 0 ? K1Y_WAVES_PER_EU : K1X_WAVES_PER_EU)
+                 : km == KM_NLC ? (dir == 0 ? 2 : 3)
+                 : 3;
+}
 
-template <int DIR, bool SOLVE, bool P32>
+template <int DIR, bool SOLVE, int KM>
 __global__ void TF_PASS_ATTR k_pass(PassParams p)
 {
     if (p.res_clear != nullptr && blockIdx.x == 0)
         for (int i = threadIdx.x; i < p.res_spread * RES_WORDS; i += BLOCK) p.res_clear[i] = 0ull;
     const int t = xcd_tile(blockIdx.x, p.tiles_x * p.tiles_y);
-    tile_body<DIR, SOLVE, P32>(p, t % p.tiles_x, t / p.tiles_x);
+    tile_body<DIR, SOLVE, KM>(p, t % p.tiles_x, t / p.tiles_x);
 }
 
 // Ensemble version: block -> (film, tile) from the work list; the film's geometry,
 // model, dt and buffer rotation come from the device tables, so one launch (and one
 // captured graph) serves every film. Films that are not iterating exit at once.
-template <int DIR, bool SOLVE, bool P32>
+template <int DIR, bool SOLVE, int KM>
 __global__ void TF_PASS_ATTR k_pass_ens(EnsParams e)
 {
     const int t = xcd_tile(blockIdx.x, e.nitems);
@@ -533,7 +547,7 @@ __global__ void TF_PASS_ATTR k_pass_ens(EnsParams e)
     p.ext = e.ext + d.roff * NEXT;
     p.res = s->red;
     p.res_spread = 1;
-    tile_body<DIR, SOLVE, P32>(p, tx, ty);
+    tile_body<DIR, SOLVE, KM>(p, tx, ty);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1003,19 +1017,25 @@ __global__ void __launch_bounds__(256) k_ens_validate(const FilmDesc *desc, Film
 }
 
 // ---- launchers -----------------------------------------------------------------------
-hipError_t launch_pass(int dir, bool solve, const PassParams &p, hipStream_t s)
+template <int KM>
+static void launch_pass_km(int dir, bool solve, const PassParams &p, hipStream_t s)
 {
     const dim3 grid(p.tiles_x * p.tiles_y), block(BLOCK);
-    if (p.M.p32) {
-        if (dir == 0 && !solve) k_pass<0, false, true><<<grid, block, 0, s>>>(p);
-        else if (dir == 0) k_pass<0, true, true><<<grid, block, 0, s>>>(p);
-        else if (!solve) k_pass<1, false, true><<<grid, block, 0, s>>>(p);
-        else k_pass<1, true, true><<<grid, block, 0, s>>>(p);
-    } else {
-        if (dir == 0 && !solve) k_pass<0, false, false><<<grid, block, 0, s>>>(p);
-        else if (dir == 0) k_pass<0, true, false><<<grid, block, 0, s>>>(p);
-        else if (!solve) k_pass<1, false, false><<<grid, block, 0, s>>>(p);
-        else k_pass<1, true, false><<<grid, block, 0, s>>>(p);
+    if (dir == 0 && !solve) k_pass<0, false, KM><<<grid, block, 0, s>>>(p);
+    else if (dir == 0) k_pass<0, true, KM><<<grid, block, 0, s>>>(p);
+    else if (!solve) k_pass<1, false, KM><<<grid, block, 0, s>>>(p);
+    else k_pass<1, true, KM><<<grid, block, 0, s>>>(p);
+}
+
+hipError_t launch_pass(int dir, bool solve, const PassParams &p, hipStream_t s)
+{
+    switch (p.M.kind) {
+    case MODEL_LINEAR: launch_pass_km<KM_LINEAR>(dir, solve, p, s); break;
+    case MODEL_NLC: launch_pass_km<KM_NLC>(dir, solve, p, s); break;
+    case MODEL_POLYMER: launch_pass_km<KM_POLYMER>(dir, solve, p, s); break;
+    default:
+        if (p.M.p32) launch_pass_km<KM_P32>(dir, solve, p, s);
+        else launch_pass_km<KM_POWER>(dir, solve, p, s);
     }
     return hipGetLastError();
 }
@@ -1087,15 +1107,15 @@ hipError_t launch_pass_ens(int dir, bool solve, bool p32, const EnsParams &e, hi
 {
     const dim3 grid(e.nitems), block(BLOCK);
     if (p32) {
-        if (dir == 0 && !solve) k_pass_ens<0, false, true><<<grid, block, 0, s>>>(e);
-        else if (dir == 0) k_pass_ens<0, true, true><<<grid, block, 0, s>>>(e);
-        else if (!solve) k_pass_ens<1, false, true><<<grid, block, 0, s>>>(e);
-        else k_pass_ens<1, true, true><<<grid, block, 0, s>>>(e);
+        if (dir == 0 && !solve) k_pass_ens<0, false, KM_P32><<<grid, block, 0, s>>>(e);
+        else if (dir == 0) k_pass_ens<0, true, KM_P32><<<grid, block, 0, s>>>(e);
+        else if (!solve) k_pass_ens<1, false, KM_P32><<<grid, block, 0, s>>>(e);
+        else k_pass_ens<1, true, KM_P32><<<grid, block, 0, s>>>(e);
     } else {
-        if (dir == 0 && !solve) k_pass_ens<0, false, false><<<grid, block, 0, s>>>(e);
-        else if (dir == 0) k_pass_ens<0, true, false><<<grid, block, 0, s>>>(e);
-        else if (!solve) k_pass_ens<1, false, false><<<grid, block, 0, s>>>(e);
-        else k_pass_ens<1, true, false><<<grid, block, 0, s>>>(e);
+        if (dir == 0 && !solve) k_pass_ens<0, false, KM_POWER><<<grid, block, 0, s>>>(e);
+        else if (dir == 0) k_pass_ens<0, true, KM_POWER><<<grid, block, 0, s>>>(e);
+        else if (!solve) k_pass_ens<1, false, KM_POWER><<<grid, block, 0, s>>>(e);
+        else k_pass_ens<1, true, KM_POWER><<<grid, block, 0, s>>>(e);
     }
     return hipGetLastError();
 }
