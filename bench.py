@@ -53,13 +53,13 @@ def traffic_for(kernel, ncells):
     return (k["fetch_kib"] + k["write_kib"]) * 1024.0 * t.get("copy_scale", 1.0)
 
 
-def cpu_baseline(h_np, ds, dt, iters_per_step):
+def cpu_baseline(h_np, ds, dt, iters_per_step, model="power"):
     """Oracle (plain C, OpenMP over lines) timed for ONE Newton iteration of the same
     film; steps/s = 1 / (t_iteration * mean Newton iterations per step of the GPU run)."""
     from oracle import oracle as orc
     threads = len(os.sched_getaffinity(0))
     orc.set_threads(threads)
-    M = orc.Model(kappa=10.0, b=0.1, n=3.0, m=2.0)
+    M = orc.Model(kappa=10.0, b=0.1, n=3.0, m=2.0) if model == "power" else getattr(orc.Model, model)()
     t0 = time.perf_counter()
     orc.adi_iteration(M, h_np, h_np, ds, dt, 1.0)
     t_it = time.perf_counter() - t0
@@ -259,6 +259,10 @@ def main():
                          "adjoint: 512^2 gradient by the checkpointed adjoint; "
                          "spectrum: radial Fourier transform of a 4000^2 film")
     ap.add_argument("--films", type=int, default=256)
+    ap.add_argument("--model", default="power", choices=["power", "nlc", "polymer"],
+                    help="single workload only: the power law of the default workload, or the NLC "
+                         "(H0 = 0.5) / polymer (H0 = 3.9) film on the same grid with L = 256 lambda_m "
+                         "and the same dt * omega_m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
@@ -299,14 +303,28 @@ def main():
 
     cfg = synth.CONFIGS[args.config]
     n = cfg.n
-    h_np = cfg.film()
     dev = torch.device("cuda:0")
+    if args.model == "power":
+        h_np, ds, dt0 = cfg.film(), cfg.ds, cfg.dt
+        g = Grid(n, n, ds)
+        g.set_model(cfg.kappa, cfg.b, cfg.nexp, cfg.mexp)
+        workload = (f"{cfg.name}: {n}x{n} film, L={cfg.periods:g} lambda_m, noise 0.01 seed {cfg.seed}, "
+                    f"backward Euler dt={cfg.dt}, tol {cfg.tol}, fixed dt")
+    else:
+        from paper_1806_10550_amd.validate import lsa_params
+        h0, _, _, qm, wm = lsa_params(args.model)
+        ds = cfg.periods * 2 * math.pi / qm / n
+        dt0 = cfg.dt * synth.omega_m(cfg.kappa, cfg.b, cfg.nexp, cfg.mexp) / wm
+        h_np = synth.noise_film(n, n, cfg.seed, h0, 0.01 * h0)
+        g = Grid(n, n, ds)
+        getattr(g, "set_model_" + args.model)()
+        workload = (f"{args.model}{n}: {n}x{n} {args.model.upper()} film at H0={h0}, L={cfg.periods:g} lambda_m, "
+                    f"noise 0.01 H0 seed {cfg.seed}, backward Euler dt={dt0:.4g} (dt omega_m as {cfg.name}), "
+                    f"tol {cfg.tol}, fixed dt")
     h = torch.from_numpy(h_np).to(dev)
-    g = Grid(n, n, cfg.ds)
-    g.set_model(cfg.kappa, cfg.b, cfg.nexp, cfg.mexp)
     g.set_scheme(theta=1.0, tol=cfg.tol, max_newton=5000, adaptive=cfg.adaptive)
     g.bind(h)
-    dt = cfg.dt
+    dt = dt0
     if args.warmup > 0:
         dt, _ = g.advance(args.warmup, dt)
     torch.cuda.synchronize()
@@ -329,7 +347,8 @@ def main():
     avg_s = ms / 1e3 / max(cnt, 1)
     algo_bytes = ALGO_BYTES_PER_CELL[dom] * ncells
     achieved = algo_bytes / avg_s / 1e9
-    traffic = traffic_for(dom, ncells)
+    # the counter summary covers the n = 3, m = 2 kernels only
+    traffic = traffic_for(dom, ncells) if args.model == "power" else None
     kernel_ms = sum(v[0] for v in prof.values())
     iter_frac = (48.0 * ncells * total_iters) / (elapsed * HBM_PEAK_GBS * 1e9)
 
@@ -346,9 +365,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: {n}x{n} film, L=256 lambda_m, noise 0.01 seed {cfg.seed}, "
-                               f"backward Euler dt={cfg.dt}, tol {cfg.tol}, fixed dt",
-                   "nx": n, "ny": n, "dt": cfg.dt, "tol": cfg.tol},
+        "config": {"workload": workload, "nx": n, "ny": n, "dt": dt0, "tol": cfg.tol},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
@@ -362,7 +379,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         h_now = h.cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(h_now, cfg.ds, dt, total_iters / args.steps)
+        out["cpu_baseline"] = cpu_baseline(h_now, ds, dt, total_iters / args.steps, args.model)
     print(json.dumps(out), flush=True)
     g.close()
 
