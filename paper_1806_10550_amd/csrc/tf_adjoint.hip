@@ -150,11 +150,17 @@ struct SBParams {
 
 // Partitioned solve over tiles of 64 lines x 64 cells (4 waves x 16-cell sub-segments):
 // SOLVE false emits the tile's relation record per line, SOLVE true back-substitutes.
-template <bool SOLVE, bool TRANS, int MODE>
+// ROWIO: rhs (and, MODE 0, out) are line-major [line][position] instead of [position][line];
+// the tile's 64 x 64 block goes through LDS so that global accesses stay coalesced (this
+// spares the row solves of the adjoint a transpose in and a transpose out).
+template <bool SOLVE, bool TRANS, int MODE, bool ROWIO = false>
 __global__ void __launch_bounds__(BLOCK) k_sb_pass(SBParams P)
 {
+    static_assert(!(ROWIO && MODE == 1), "line-major output is for MODE 0");
+    constexpr int RP = TILE + 1; // LDS pitch of the line-major staging tile
     __shared__ double sB[NSUB * NREL * 64];
     __shared__ double sRed[NSUB][2];
+    __shared__ double sR[ROWIO ? TILE * RP : 1];
     const int nlg = (P.nl + 63) / 64;
     const int t = xcd_tile(blockIdx.x, nlg * seg_count(P.np));
     const int lg = t % nlg, q = t / nlg;
@@ -168,6 +174,15 @@ __global__ void __launch_bounds__(BLOCK) k_sb_pass(SBParams P)
     const int ps = (wave * npos) / nsub;
     const int len = wave < nsub ? ((wave + 1) * npos) / nsub - ps : 0;
     const size_t N = (size_t)P.nl * P.np;
+    if (ROWIO) {
+        // sR[k * RP + l] = rhs of line lg*64 + l (clamped) at position s0 + k
+        for (int e = tid; e < 64 * npos; e += BLOCK) {
+            const int l = e / npos, k = e - l * npos;
+            const int gl = min(lg * 64 + l, P.nl - 1);
+            sR[k * RP + l] = P.rhs[(size_t)gl * P.np + s0 + k];
+        }
+        __syncthreads();
+    }
     double fa[SUB], fb[SUB], fz[SUB], fph[SUB], fps[SUB];
     Rel mine;
     if (len > 0) {
@@ -178,7 +193,7 @@ __global__ void __launch_bounds__(BLOCK) k_sb_pass(SBParams P)
                 const int p = s0 + ps + k;
                 double a, b, c, d, e;
                 load_band_row<TRANS>(P.bands, N, P.nl, P.np, p, lc, a, b, c, d, e);
-                const double rhs = P.rhs[(size_t)p * P.nl + lc];
+                const double rhs = ROWIO ? sR[(ps + k) * RP + lane] : P.rhs[(size_t)p * P.nl + lc];
                 double al, be, z, ph, pss;
                 E.step(k, a, b, c, d, e, rhs, al, be, z, ph, pss);
                 if (SOLVE) { fa[k] = al; fb[k] = be; fz[k] = z; fph[k] = ph; fps[k] = pss; }
@@ -224,7 +239,9 @@ __global__ void __launch_bounds__(BLOCK) k_sb_pass(SBParams P)
                 const double x = fz[k] + fph[k] * wl1 + fps[k] * wl2 - fa[k] * xr1 - fb[k] * xr2;
                 xr2 = xr1;
                 xr1 = x;
-                if (owned) {
+                if (ROWIO) {
+                    sR[(ps + k) * RP + lane] = x; // every rhs read happened before the exchange barrier
+                } else if (owned) {
                     const size_t o = (size_t)(s0 + ps + k) * P.nl + line;
                     if (MODE == 0) {
                         P.out[o] = x;
@@ -236,6 +253,14 @@ __global__ void __launch_bounds__(BLOCK) k_sb_pass(SBParams P)
                             }
                 }
             }
+        }
+    }
+    if (ROWIO) {
+        __syncthreads();
+        for (int e = tid; e < 64 * npos; e += BLOCK) {
+            const int l = e / npos, k = e - l * npos;
+            const int gl = lg * 64 + l;
+            if (gl < P.nl) P.out[(size_t)gl * P.np + s0 + k] = sR[k * RP + l];
         }
     }
     if (MODE == 1) {
@@ -625,10 +650,13 @@ struct Scratch {
     double *rel = nullptr, *ext = nullptr, *chain = nullptr, *work = nullptr;
 };
 
+// rowio: rhs and out line-major (partitioned variant, transposed MODE 0 solves only).
 tf_status sb_solve(Choice ch, bool trans, int mode, int nl, int np, const double *bands, const double *rhs,
-                   double *out, unsigned long long *red, const Scratch &S, hipStream_t s)
+                   double *out, unsigned long long *red, const Scratch &S, hipStream_t s, bool rowio = false)
 {
     tf::SBParams P{nl, np, bands, rhs, out, S.rel, S.ext, red};
+    if (rowio && (ch.variant != V_PARTITIONED || !trans || mode != 0))
+        return afail(TF_EINVAL, "line-major solves need the partitioned transposed MODE 0 variant");
     if (ch.variant == V_PCR) {
         if (np > tf::PCR_MAX) return afail(TF_EINVAL, "cyclic reduction needs lines of at most 2048 cells");
         const dim3 g(nl), b(tf::PCR_THREADS);
@@ -651,12 +679,14 @@ tf_status sb_solve(Choice ch, bool trans, int mode, int nl, int np, const double
     }
     const int ntile = ((nl + 63) / 64) * tf::seg_count(np);
     const dim3 g(ntile), b(tf::BLOCK);
-    if (trans) tf::k_sb_pass<false, true, 0><<<g, b, 0, s>>>(P);
+    if (rowio) tf::k_sb_pass<false, true, 0, true><<<g, b, 0, s>>>(P);
+    else if (trans) tf::k_sb_pass<false, true, 0><<<g, b, 0, s>>>(P);
     else tf::k_sb_pass<false, false, 0><<<g, b, 0, s>>>(P);
     TF_AHIP(hipGetLastError());
     tf::ChainParams C{nl, tf::seg_count(np), S.rel, S.chain, S.ext};
     TF_AHIP(tf::launch_chain(C, s));
-    if (trans && mode == 0) tf::k_sb_pass<true, true, 0><<<g, b, 0, s>>>(P);
+    if (rowio) tf::k_sb_pass<true, true, 0, true><<<g, b, 0, s>>>(P);
+    else if (trans && mode == 0) tf::k_sb_pass<true, true, 0><<<g, b, 0, s>>>(P);
     else if (trans) tf::k_sb_pass<true, true, 1><<<g, b, 0, s>>>(P);
     else if (mode == 0) tf::k_sb_pass<true, false, 0><<<g, b, 0, s>>>(P);
     else tf::k_sb_pass<true, false, 1><<<g, b, 0, s>>>(P);
@@ -838,10 +868,15 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
         // r = lambda - (I + c J^T) mu
         // (the reduction words of this iteration's y solve are zeroed by the same kernel)
         if ((st = jdt(v, h_np1, B.mu, lambda_inout, 1.0, -1.0, -c, B.r, B, B.red)) != TF_OK) return st;
-        if ((st = transpose(ny, nx, B.r, B.rT, s)) != TF_OK) return st;
-        // (I + c J_x)^-T: rows as lines (transposed layout [i][j])
-        if ((st = sb_solve(vx, true, 0, ny, nx, B.bx, B.rT, B.yT, nullptr, S, s)) != TF_OK) return st;
-        if ((st = transpose(nx, ny, B.yT, B.y, s)) != TF_OK) return st;
+        // (I + c J_x)^-T: rows as lines; the partitioned solver reads r and writes y row by
+        // row through LDS, the other variants work on the transposed layout [i][j]
+        if (vx.variant == V_PARTITIONED) {
+            if ((st = sb_solve(vx, true, 0, ny, nx, B.bx, B.r, B.y, nullptr, S, s, true)) != TF_OK) return st;
+        } else {
+            if ((st = transpose(ny, nx, B.r, B.rT, s)) != TF_OK) return st;
+            if ((st = sb_solve(vx, true, 0, ny, nx, B.bx, B.rT, B.yT, nullptr, S, s)) != TF_OK) return st;
+            if ((st = transpose(nx, ny, B.yT, B.y, s)) != TF_OK) return st;
+        }
         // (I + c J_y)^-T: columns as lines; mu += z with max|z|, max|mu|
         if ((st = sb_solve(vy, true, 1, nx, ny, B.by, B.y, B.mu, B.red, S, s)) != TF_OK) return st;
         TF_AHIP(hipMemcpyAsync(B.hred, B.red, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
