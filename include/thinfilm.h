@@ -163,6 +163,14 @@ const char *tf_profile_names(void);
 typedef struct tf_ensemble tf_ensemble;
 tf_status tf_ensemble_create(int nfilms, const int *nx, const int *ny, const double *ds, const double *kappa,
                              double b, double n, double m, void *stream, tf_ensemble **out);
+/* Give every film of the ensemble the linear, NLC or polymer model instead of the power law
+ * of tf_ensemble_create (same parameters and checks as tf_set_model_linear, tf_set_model_nlc
+ * and tf_set_model_polymer; the per-film kappa is then unused). Films may still differ in
+ * size, ds and initial thickness. Waits for the ensemble's stream; TF_EINVAL for rejected
+ * parameters. */
+tf_status tf_ensemble_set_model_linear(tf_ensemble *e, double c0, double c1);
+tf_status tf_ensemble_set_model_nlc(tf_ensemble *e, double C, double K, double N, double beta, double w, double b);
+tf_status tf_ensemble_set_model_polymer(tf_ensemble *e, double C, double Cst, double Aox, double Asi, double d);
 tf_status tf_ensemble_destroy(tf_ensemble *e);
 /* scheme as for tf_set_scheme; theta must be 1 (TF_EINVAL otherwise) */
 tf_status tf_ensemble_set_scheme(tf_ensemble *e, const tf_scheme *s);

@@ -45,6 +45,71 @@ constexpr int RES_STRIDE = tf::RES_SPREAD * tf::RES_WORDS; // words per reductio
 
 namespace tf_detail {
 void set_error(const std::string &msg) { g_err = msg; }
+
+// Model records of the linear, NLC and polymer models (see tf::Model); false with a message
+// for parameters the models do not admit (M is then left unchanged).
+bool linear_model(double c0, double c1, tf::Model *M, std::string *err)
+{
+    if (!(c0 > 0.0) || !std::isfinite(c0) || !std::isfinite(c1)) {
+        *err = "need finite c0 > 0 and c1";
+        return false;
+    }
+    tf::Model m{};
+    m.kind = tf::MODEL_LINEAR;
+    m.cap = c0;
+    m.Cm = c1;
+    *M = m;
+    return true;
+}
+
+bool nlc_model(double C, double K, double N, double beta, double w, double b, tf::Model *M, std::string *err)
+{
+    const double v[6] = {C, K, N, beta, w, b};
+    for (double x : v)
+        if (!std::isfinite(x)) {
+            *err = "NLC parameters must be finite";
+            return false;
+        }
+    if (!(C > 0.0) || !(w > 0.0) || !(b > 0.0) || !(K >= 0.0) || !(N >= 0.0)) {
+        *err = "need C > 0, w > 0, b > 0, K >= 0 and N >= 0";
+        return false;
+    }
+    tf::Model m{};
+    m.kind = tf::MODEL_NLC;
+    m.cap = C;
+    m.K = K;
+    m.N = N;
+    m.beta2 = beta * beta;
+    m.w = w;
+    m.iw = 1.0 / w;
+    m.b = b;
+    *M = m;
+    return true;
+}
+
+bool polymer_model(double C, double Cst, double Aox, double Asi, double d, tf::Model *M, std::string *err)
+{
+    const double v[5] = {C, Cst, Aox, Asi, d};
+    for (double x : v)
+        if (!std::isfinite(x)) {
+            *err = "polymer parameters must be finite";
+            return false;
+        }
+    if (!(C > 0.0) || !(d >= 0.0)) {
+        *err = "need C > 0 and d >= 0";
+        return false;
+    }
+    tf::Model m{};
+    m.kind = tf::MODEL_POLYMER;
+    m.cap = C;
+    // Pi = -psi' = 8 Cst h^-9 - (Aox/(6 pi)) h^-3 + ((Aox - Asi)/(6 pi)) (h+d)^-3
+    m.C8 = 8.0 * Cst;
+    m.a2 = Aox / (6.0 * M_PI);
+    m.c2 = (Aox - Asi) / (6.0 * M_PI);
+    m.d = d;
+    *M = m;
+    return true;
+}
 } // namespace tf_detail
 
 struct tf_grid {
@@ -451,12 +516,8 @@ tf_status tf_set_model(tf_grid *g, double kappa, double b, double n, double m)
 tf_status tf_set_model_linear(tf_grid *g, double c0, double c1)
 {
     if (g == nullptr) return fail(TF_EINVAL, "grid is NULL");
-    if (!(c0 > 0.0) || !std::isfinite(c0) || !std::isfinite(c1)) return fail(TF_EINVAL, "need finite c0 > 0 and c1");
-    tf::Model M{};
-    M.kind = tf::MODEL_LINEAR;
-    M.cap = c0;
-    M.Cm = c1;
-    g->M = M;
+    std::string err;
+    if (!tf_detail::linear_model(c0, c1, &g->M, &err)) return fail(TF_EINVAL, err);
     g->model_set = true;
     g->state_ok = false;
     return TF_OK;
@@ -465,21 +526,8 @@ tf_status tf_set_model_linear(tf_grid *g, double c0, double c1)
 tf_status tf_set_model_nlc(tf_grid *g, double C, double K, double N, double beta, double w, double b)
 {
     if (g == nullptr) return fail(TF_EINVAL, "grid is NULL");
-    const double v[6] = {C, K, N, beta, w, b};
-    for (double x : v)
-        if (!std::isfinite(x)) return fail(TF_EINVAL, "NLC parameters must be finite");
-    if (!(C > 0.0) || !(w > 0.0) || !(b > 0.0)) return fail(TF_EINVAL, "need C > 0, w > 0 and b > 0");
-    if (!(K >= 0.0) || !(N >= 0.0)) return fail(TF_EINVAL, "need K >= 0 and N >= 0");
-    tf::Model M{};
-    M.kind = tf::MODEL_NLC;
-    M.cap = C;
-    M.K = K;
-    M.N = N;
-    M.beta2 = beta * beta;
-    M.w = w;
-    M.iw = 1.0 / w;
-    M.b = b;
-    g->M = M;
+    std::string err;
+    if (!tf_detail::nlc_model(C, K, N, beta, w, b, &g->M, &err)) return fail(TF_EINVAL, err);
     g->model_set = true;
     g->state_ok = false;
     return TF_OK;
@@ -488,19 +536,8 @@ tf_status tf_set_model_nlc(tf_grid *g, double C, double K, double N, double beta
 tf_status tf_set_model_polymer(tf_grid *g, double C, double Cst, double Aox, double Asi, double d)
 {
     if (g == nullptr) return fail(TF_EINVAL, "grid is NULL");
-    const double v[5] = {C, Cst, Aox, Asi, d};
-    for (double x : v)
-        if (!std::isfinite(x)) return fail(TF_EINVAL, "polymer parameters must be finite");
-    if (!(C > 0.0) || !(d >= 0.0)) return fail(TF_EINVAL, "need C > 0 and d >= 0");
-    tf::Model M{};
-    M.kind = tf::MODEL_POLYMER;
-    M.cap = C;
-    // Pi = -psi' = 8 Cst h^-9 - (Aox/(6 pi)) h^-3 + ((Aox - Asi)/(6 pi)) (h+d)^-3
-    M.C8 = 8.0 * Cst;
-    M.a2 = Aox / (6.0 * M_PI);
-    M.c2 = (Aox - Asi) / (6.0 * M_PI);
-    M.d = d;
-    g->M = M;
+    std::string err;
+    if (!tf_detail::polymer_model(C, Cst, Aox, Asi, d, &g->M, &err)) return fail(TF_EINVAL, err);
     g->model_set = true;
     g->state_ok = false;
     return TF_OK;

@@ -49,7 +49,7 @@ struct tf_ensemble {
     int *d_active = nullptr, *h_active = nullptr;
     double *buf0 = nullptr, *buf1 = nullptr, *buf2 = nullptr, *w = nullptr;
     double *rel = nullptr, *ext = nullptr, *chain = nullptr;
-    bool p32 = true;
+    int km = tf::KM_P32; // model form of the sweep kernels (one model for every film)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int prev_iters = 4;
@@ -84,12 +84,12 @@ tf_status enqueue_iteration(tf_ensemble *e)
 {
     const tf::EnsScheme S{e->S.theta, e->S.tol, e->S.dt_min, e->S.dt_max, e->S.dt_shrink, e->S.dt_grow,
                           e->S.max_newton, e->S.grow_after, e->S.adaptive};
-    TF_EHIP(tf::launch_pass_ens(0, false, e->p32, params(e, 0), e->stream));
+    TF_EHIP(tf::launch_pass_ens(0, false, e->km, params(e, 0), e->stream));
     TF_EHIP(tf::launch_chain_ens(params(e, 2), 0, e->stream));
-    TF_EHIP(tf::launch_pass_ens(0, true, e->p32, params(e, 0), e->stream));
-    TF_EHIP(tf::launch_pass_ens(1, false, e->p32, params(e, 1), e->stream));
+    TF_EHIP(tf::launch_pass_ens(0, true, e->km, params(e, 0), e->stream));
+    TF_EHIP(tf::launch_pass_ens(1, false, e->km, params(e, 1), e->stream));
     TF_EHIP(tf::launch_chain_ens(params(e, 3), 1, e->stream));
-    TF_EHIP(tf::launch_pass_ens(1, true, e->p32, params(e, 1), e->stream));
+    TF_EHIP(tf::launch_pass_ens(1, true, e->km, params(e, 1), e->stream));
     TF_EHIP(tf::launch_ens_control(e->d_state, e->nfilms, S, e->d_active, e->stream));
     return TF_OK;
 }
@@ -119,6 +119,18 @@ tf_status ensure_graph(tf_ensemble *e)
     return TF_OK;
 }
 
+// Replace every film's model by M (kernel form km) and upload the film table.
+tf_status set_all_models(tf_ensemble *e, const tf::Model &M, int km)
+{
+    for (auto &d : e->desc) d.M = M;
+    TF_EHIP(hipMemcpyAsync(e->d_desc, e->desc.data(), e->nfilms * sizeof(tf::FilmDesc), hipMemcpyHostToDevice,
+                           e->stream));
+    TF_EHIP(hipStreamSynchronize(e->stream));
+    e->km = km;
+    drop_graph(e);
+    return TF_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -137,7 +149,8 @@ tf_status tf_ensemble_create(int nfilms, const int *nx, const int *ny, const dou
     e->nfilms = nfilms;
     e->user = (hipStream_t)stream;
     e->S = tf_scheme{1.0, 1e-10, 1e-6, 1.0, 0.5, 1.1, 5000, 5, 0};
-    e->p32 = ((int)n == 3 && (int)m == 2);
+    const bool p32 = ((int)n == 3 && (int)m == 2);
+    e->km = p32 ? tf::KM_P32 : tf::KM_POWER;
     std::vector<int> items_y, items_x, items_cy, items_cx;
     for (int f = 0; f < nfilms; ++f) {
         if (nx[f] < 4 || ny[f] < 4 || !(ds[f] > 0.0) || !std::isfinite(kappa[f])) {
@@ -159,7 +172,7 @@ tf_status tf_ensemble_create(int nfilms, const int *nx, const int *ny, const dou
         M.Cm = kappa[f] * m * std::pow(b, m);
         M.Dn = kappa[f] * n * (n - 2.0) * std::pow(b, n);
         M.Dm = kappa[f] * m * (m - 2.0) * std::pow(b, m);
-        M.p32 = e->p32;
+        M.p32 = p32;
         M.kind = tf::MODEL_POWER;
         M.cap = 1.0;
         d.M = M;
@@ -261,6 +274,33 @@ tf_status tf_ensemble_set_scheme(tf_ensemble *e, const tf_scheme *s)
     e->S = *s;
     drop_graph(e);
     return TF_OK;
+}
+
+tf_status tf_ensemble_set_model_linear(tf_ensemble *e, double c0, double c1)
+{
+    if (e == nullptr) return efail(TF_EINVAL, "ensemble is NULL");
+    tf::Model M;
+    std::string err;
+    if (!tf_detail::linear_model(c0, c1, &M, &err)) return efail(TF_EINVAL, err);
+    return set_all_models(e, M, tf::KM_LINEAR);
+}
+
+tf_status tf_ensemble_set_model_nlc(tf_ensemble *e, double C, double K, double N, double beta, double w, double b)
+{
+    if (e == nullptr) return efail(TF_EINVAL, "ensemble is NULL");
+    tf::Model M;
+    std::string err;
+    if (!tf_detail::nlc_model(C, K, N, beta, w, b, &M, &err)) return efail(TF_EINVAL, err);
+    return set_all_models(e, M, tf::KM_NLC);
+}
+
+tf_status tf_ensemble_set_model_polymer(tf_ensemble *e, double C, double Cst, double Aox, double Asi, double d)
+{
+    if (e == nullptr) return efail(TF_EINVAL, "ensemble is NULL");
+    tf::Model M;
+    std::string err;
+    if (!tf_detail::polymer_model(C, Cst, Aox, Asi, d, &M, &err)) return efail(TF_EINVAL, err);
+    return set_all_models(e, M, tf::KM_POLYMER);
 }
 
 tf_status tf_ensemble_bind(tf_ensemble *e, double *packed_dev)

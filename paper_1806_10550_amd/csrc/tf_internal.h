@@ -140,7 +140,7 @@ hipError_t launch_flux_divergence(int nx, int ny, double ids, double ids2, const
                                   const double *u, double alpha, double beta, const double *add,
                                   double *out, hipStream_t s);
 hipError_t launch_mass(const double *u, size_t n, double *partials, int nblocks, hipStream_t s);
-hipError_t launch_pass_ens(int dir, bool solve, bool p32, const EnsParams &e, hipStream_t s);
+hipError_t launch_pass_ens(int dir, bool solve, int km, const EnsParams &e, hipStream_t s);
 hipError_t launch_chain_ens(const EnsParams &e, int dir, hipStream_t s);
 hipError_t launch_ens_control(FilmState *st, int nfilms, const EnsScheme &S, int *active_count, hipStream_t s);
 hipError_t launch_ens_begin(FilmState *st, int nfilms, hipStream_t s);
@@ -163,4 +163,7 @@ struct GridView {
 bool grid_view(const tf_grid *g, GridView *v);   // false if the model is not set
 void release_adjoint(const tf_grid *g);           // frees adjoint scratch of a grid
 void set_error(const std::string &msg);
+bool linear_model(double c0, double c1, tf::Model *M, std::string *err);
+bool nlc_model(double C, double K, double N, double beta, double w, double b, tf::Model *M, std::string *err);
+bool polymer_model(double C, double Cst, double Aox, double Asi, double d, tf::Model *M, std::string *err);
 } // namespace tf_detail

@@ -1103,19 +1103,25 @@ hipError_t launch_mass(const double *u, size_t n, double *partials, int nblocks,
 
 namespace tf {
 
-hipError_t launch_pass_ens(int dir, bool solve, bool p32, const EnsParams &e, hipStream_t s)
+template <int KM>
+static void launch_pass_ens_km(int dir, bool solve, const EnsParams &e, hipStream_t s)
 {
     const dim3 grid(e.nitems), block(BLOCK);
-    if (p32) {
-        if (dir == 0 && !solve) k_pass_ens<0, false, KM_P32><<<grid, block, 0, s>>>(e);
-        else if (dir == 0) k_pass_ens<0, true, KM_P32><<<grid, block, 0, s>>>(e);
-        else if (!solve) k_pass_ens<1, false, KM_P32><<<grid, block, 0, s>>>(e);
-        else k_pass_ens<1, true, KM_P32><<<grid, block, 0, s>>>(e);
-    } else {
-        if (dir == 0 && !solve) k_pass_ens<0, false, KM_POWER><<<grid, block, 0, s>>>(e);
-        else if (dir == 0) k_pass_ens<0, true, KM_POWER><<<grid, block, 0, s>>>(e);
-        else if (!solve) k_pass_ens<1, false, KM_POWER><<<grid, block, 0, s>>>(e);
-        else k_pass_ens<1, true, KM_POWER><<<grid, block, 0, s>>>(e);
+    if (dir == 0 && !solve) k_pass_ens<0, false, KM><<<grid, block, 0, s>>>(e);
+    else if (dir == 0) k_pass_ens<0, true, KM><<<grid, block, 0, s>>>(e);
+    else if (!solve) k_pass_ens<1, false, KM><<<grid, block, 0, s>>>(e);
+    else k_pass_ens<1, true, KM><<<grid, block, 0, s>>>(e);
+}
+
+// km: the KernelModel every film of the ensemble shares
+hipError_t launch_pass_ens(int dir, bool solve, int km, const EnsParams &e, hipStream_t s)
+{
+    switch (km) {
+    case KM_P32: launch_pass_ens_km<KM_P32>(dir, solve, e, s); break;
+    case KM_POWER: launch_pass_ens_km<KM_POWER>(dir, solve, e, s); break;
+    case KM_LINEAR: launch_pass_ens_km<KM_LINEAR>(dir, solve, e, s); break;
+    case KM_NLC: launch_pass_ens_km<KM_NLC>(dir, solve, e, s); break;
+    default: launch_pass_ens_km<KM_POLYMER>(dir, solve, e, s); break;
     }
     return hipGetLastError();
 }

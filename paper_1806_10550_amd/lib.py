@@ -64,6 +64,9 @@ def lib():
         L.tf_spectrum_maxima.argtypes = [P, P, C.c_int, D, C.c_int, P, P, P, C.c_int, P]
         L.tf_model_coeffs.argtypes = [P, P, C.c_int, P]
         L.tf_set_model_nlc.argtypes = [P, D, D, D, D, D, D]
+        L.tf_ensemble_set_model_linear.argtypes = [P, D, D]
+        L.tf_ensemble_set_model_nlc.argtypes = [P, D, D, D, D, D, D]
+        L.tf_ensemble_set_model_polymer.argtypes = [P, D, D, D, D, D]
         L.tf_set_model_polymer.argtypes = [P, D, D, D, D, D]
         L.tf_set_scheme.argtypes = [P, C.POINTER(Scheme)]
         L.tf_get_scheme.argtypes = [P, C.POINTER(Scheme)]
@@ -289,6 +292,20 @@ class Ensemble:
         self.offsets = [int(v) for v in offs]
         self.size = int(lib().tf_ensemble_size(self._h))
         self._state = None
+
+    def set_model_linear(self, c0=1.0, c1=1.0):
+        _check(lib().tf_ensemble_set_model_linear(self._h, float(c0), float(c1)))
+        return self
+
+    def set_model_nlc(self, C=0.0857, K=36.0, N=1.67, beta=1.0, w=0.05, b=0.01):
+        """Every film gets the NLC model (eqs. DisjPressNLC, mh_model; defaults eq. NLC_paras)."""
+        _check(lib().tf_ensemble_set_model_nlc(self._h, *(float(x) for x in (C, K, N, beta, w, b))))
+        return self
+
+    def set_model_polymer(self, C=0.00581, Cst=1.181, Aox=41.25, Asi=-243.75, d=191.0):
+        """Every film gets the polymer model (eq. DisjPressPolymer; defaults eq. Polymer_scales)."""
+        _check(lib().tf_ensemble_set_model_polymer(self._h, *(float(x) for x in (C, Cst, Aox, Asi, d))))
+        return self
 
     def close(self):
         if self._h:

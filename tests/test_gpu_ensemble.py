@@ -111,3 +111,48 @@ def test_ensemble_adaptive_schedules_match_single_films():
         assert s1 == TF_OK
         assert dts[f] == dtn
         assert torch.equal(ens.view(packed, f), h), f
+
+
+@pytest.mark.parametrize("kind,h0s,dt", [("nlc", (0.3, 0.5, 0.7), 0.05), ("polymer", (3.0, 3.9, 5.0), 1e-3)])
+def test_model_ensemble_equals_single_film_path_bitwise(orc, kind, h0s, dt):
+    """Films of the NLC or polymer model with different sizes and thicknesses H0 (each on
+    8 of its own most unstable wavelengths) advance in one ensemble exactly as one by one."""
+    import math
+    sizes = [(70, 66), (130, 40), (96, 97)]
+    M = getattr(orc.Model, kind)()
+    nx, ny, ds, h0 = [], [], [], []
+    for i, ((a, b), H) in enumerate(zip(sizes, h0s)):
+        f0, _, f1, _ = orc.coeffs(M, H)
+        lam = 2 * math.pi / math.sqrt(f1 / (2 * f0))
+        nx.append(a)
+        ny.append(b)
+        ds.append(8 * lam / a)
+        h0.append(synth.noise_film(a, b, seed=300 + i, h0=H, amp=0.01 * H))
+    ens = Ensemble(nx, ny, ds, [1.0] * len(sizes))
+    getattr(ens, "set_model_" + kind)()
+    ens.set_scheme(tol=1e-10)
+    packed = pack(ens, h0)
+    ens.bind(packed)
+    st, dts, sts, its = ens.step(3, dt)
+    assert st == TF_OK and all(s == TF_OK for s in sts)
+    for f in range(len(sizes)):
+        g = Grid(nx[f], ny[f], ds[f])
+        getattr(g, "set_model_" + kind)()
+        g.set_scheme(tol=1e-10)
+        h = torch.from_numpy(h0[f]).to(DEV)
+        g.bind(h)
+        s1, _, log = g.try_advance(3, dt)
+        assert s1 == TF_OK
+        assert torch.equal(ens.view(packed, f), h), f
+        assert its[f] == sum(x["total_iters"] for x in log)
+
+
+def test_model_ensemble_rejects_bad_parameters():
+    from paper_1806_10550_amd.lib import TFError
+    ens = Ensemble([64], [64], [0.5], [10.0])
+    with pytest.raises(TFError):
+        ens.set_model_nlc(w=0.0)
+    with pytest.raises(TFError):
+        ens.set_model_polymer(C=-1.0)
+    with pytest.raises(TFError):
+        ens.set_model_linear(c0=0.0)
