@@ -39,6 +39,15 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+def copy_rate_gbs():
+    """The plain copy's measured rate from the committed counter summary (any kernel sources)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            return json.load(f).get("copy_gbs")
+    except (OSError, ValueError):
+        return None
+
+
 def traffic_for(kernel, ncells):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None when
     absent or taken on different kernel sources."""
@@ -370,6 +379,10 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
         "newton_iters_per_step": total_iters / args.steps,
+        "newton_iters_distribution": {"min": min(iters), "median": sorted(iters)[len(iters) // 2],
+                                      "max": max(iters)},
+        "copy_kernel_gbs": copy_rate_gbs(),
+        "achieved_frac_of_copy": (achieved / copy_rate_gbs()) if copy_rate_gbs() else None,
         "grid_point_steps_per_s": steps_per_s * ncells,
         "grid_point_iterations_per_s": total_iters * ncells / elapsed,
         "iteration_roofline_frac": iter_frac,

@@ -72,6 +72,16 @@ def counter_means(d, counter):
     return {k: statistics.mean(v) for k, v in per.items()}, {k: len(v) for k, v in per.items()}
 
 
+def copy_duration_us(d, counter):
+    """Mean duration of the calibration copy (the dispatches with the largest counter value)."""
+    path = _find(d, "*counter_collection.csv")
+    rows = [r for r in csv.DictReader(open(path)) if r.get("Counter_Name") == counter]
+    top = max(float(r["Counter_Value"]) for r in rows)
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows
+            if float(r["Counter_Value"]) >= 0.99 * top and "copy" in r.get("Kernel_Name", "").lower()]
+    return statistics.mean(durs) if durs else None
+
+
 # the counter runs this record summarises (repo root R on the GPU box, run from /tmp with
 # TMPDIR=/tmp); one counter per pass
 COMMANDS = [
@@ -107,6 +117,8 @@ def traffic(a):
         "fetch_scale": known_kib / cf_kib,
         "write_scale": known_kib / cw_kib,
         "copy_scale": 0.5 * (known_kib / cf_kib + known_kib / cw_kib),
+        # the plain copy's own rate (read + write of copy_bytes; measured under the counters)
+        "copy_us": copy_duration_us(a.copy_fetch, "FETCH_SIZE"),
         "kernels": {},
     }
     for name in fetch:
@@ -117,6 +129,7 @@ def traffic(a):
         rec["fetch_kib"] = fetch[name] * (known_kib / cf_kib)
         rec["write_kib"] = write.get(name, 0.0) * (known_kib / cw_kib)
         rec["dispatches"] = nf[name]
+    out["copy_gbs"] = 2.0 * a.copy_bytes / (out["copy_us"] * 1e3) if out["copy_us"] else None
     # bench.py multiplies (fetch + write) by copy_scale; the per-counter scales are
     # already applied above, so the combined scale is 1
     out["copy_scale"] = 1.0
