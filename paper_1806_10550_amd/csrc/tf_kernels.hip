@@ -210,7 +210,7 @@ __device__ __forceinline__ void sweep(const double *sU, double *sB, const double
                 // unknowns (z: constant part, ph: coefficient of l1, ps: of l2)
                 const double gam = b - a * al2;
                 const double mu = c - a * be2 - gam * al1;
-                const double rm = rcp(mu);
+                const double rm = rcp_pivot(mu);
                 const double al = (d - gam * be1) * rm;
                 const double be = e * rm;
                 const double z = (rhs - a * z2 - gam * z1) * rm;
