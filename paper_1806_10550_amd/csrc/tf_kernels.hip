@@ -50,11 +50,13 @@ namespace tf {
 // for halo lanes).
 __device__ __forceinline__ double dpp_shift(double v, int ctrl)
 {
+    // bound_ctrl set: a lane whose source lies outside the wave reads 0, so no "old" value
+    // has to be materialised first
     const long long b = __double_as_longlong(v);
-    const int lo = ctrl == 0x130 ? __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, false)
-                                 : __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, false);
-    const int hi = ctrl == 0x130 ? __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, false)
-                                 : __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+    const int lo = ctrl == 0x130 ? __builtin_amdgcn_mov_dpp((int)b, 0x130, 0xf, 0xf, true)
+                                 : __builtin_amdgcn_mov_dpp((int)b, 0x138, 0xf, 0xf, true);
+    const int hi = ctrl == 0x130 ? __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xf, 0xf, true)
+                                 : __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 __device__ __forceinline__ double lane_next(double v) { return dpp_shift(v, 0x130); } // wave_shl:1
