@@ -39,6 +39,24 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+SQ_FILE = os.path.join(ROOT, "profiles", "sq_large8192.json")
+
+
+def fp64_flops_for(kernel):
+    """FP64 flops per launch of a kernel class from the committed SQ counter summary, or None
+    when absent or taken on different kernel sources."""
+    try:
+        with open(SQ_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    v = t.get("kernels", {}).get(kernel, {}).get("SQ_INSTS_VALU_FLOPS_FP64")
+    # the counter adds each wave instruction's flops once (FMA 2, MUL/ADD 1): x 64 lanes
+    return 64.0 * v if v else None
+
+
 def copy_rate_gbs():
     """The plain copy's measured rate from the committed counter summary (any kernel sources)."""
     try:
@@ -382,6 +400,10 @@ def main():
         "newton_iters_distribution": {"min": min(iters), "median": sorted(iters)[len(iters) // 2],
                                       "max": max(iters)},
         "copy_kernel_gbs": copy_rate_gbs(),
+        # FP64 arithmetic rate of the same kernel (flops per launch from the committed SQ
+        # counters over the live mean duration) against the 78.6 TFLOP/s FP64 vector peak
+        "fp64_alu": ({"achieved": fp64_flops_for(dom) / avg_s / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                      "frac": fp64_flops_for(dom) / avg_s / 78.6e12} if fp64_flops_for(dom) else None),
         "achieved_frac_of_copy": (achieved / copy_rate_gbs()) if copy_rate_gbs() else None,
         "grid_point_steps_per_s": steps_per_s * ncells,
         "grid_point_iterations_per_s": total_iters * ncells / elapsed,

@@ -6,6 +6,8 @@
       --copy-write D4 --copy-bytes B --hash H
       per-kernel FETCH_SIZE / WRITE_SIZE per dispatch (KiB), with the scale factor that
       maps the counters onto the known byte count of a plain copy kernel, as JSON
+  python -m paper_1806_10550_amd.profsum sq DIR [DIR ...] --hash H
+      per-kernel means per dispatch of the SQ counters of the given runs, as JSON
 """
 import argparse
 import csv
@@ -136,6 +138,35 @@ def traffic(a):
     return out
 
 
+SQ_COMMANDS = [
+    "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 "
+    "SQ_INSTS_VALU_ADD_F64 SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES --output-format csv -d $R/gpurun_out/pmc_sqa -o run -- "
+    "python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+    "rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_WAIT_INST_ANY SQ_INSTS_LDS SQ_ACTIVE_INST_LDS SQ_INSTS_SALU "
+    "--output-format csv -d $R/gpurun_out/pmc_sqb -o run -- python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+    "python -m paper_1806_10550_amd.profsum sq gpurun_out/pmc_sqa gpurun_out/pmc_sqb --hash $(python bench.py --print-hash)",
+]
+
+
+def sq(dirs, khash):
+    """Per kernel class: the mean per dispatch of every SQ counter in the given runs (counters
+    summed over the device's shader engines by rocprofv3)."""
+    out = {"commands": SQ_COMMANDS, "kernel_hash": khash, "kernels": {}}
+    for d in dirs:
+        path = _find(d, "*counter_collection.csv")
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            cls = classify(r.get("Kernel_Name", ""))
+            if cls not in ("relations_y", "solve_y", "relations_x", "solve_x", "chain"):
+                continue
+            acc.setdefault(cls, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        for cls, cs in acc.items():
+            rec = out["kernels"].setdefault(cls, {})
+            for c, v in cs.items():
+                rec[c] = statistics.mean(v)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -147,9 +178,14 @@ def main():
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--hash", required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("dirs", nargs="+")
+    q.add_argument("--hash", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         print(stats(a.dir, a.title))
+    elif a.cmd == "sq":
+        print(json.dumps(sq(a.dirs, a.hash), indent=1))
     else:
         print(json.dumps(traffic(a), indent=1))
 
