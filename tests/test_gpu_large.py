@@ -109,3 +109,28 @@ def test_2048_long_run_mass_and_positivity():
             assert abs(x["mass"] - m0) <= 1e-12 * m0
             assert x["hmin"] > 0.0
     assert torch.isfinite(h).all()
+
+
+@pytest.mark.parametrize("name", ["spinodal2048", "nucleation2048"])
+def test_2048_through_rupture(name):
+    """The two 2048^2 films of the benchmark set, 2000 adaptive steps from dt = 0.1 (K = 10):
+    every step is accepted in the end, mass is conserved to 1e-12 at every step, h stays
+    positive, and the film reaches the precursor scale (min h < 0.2, b = 0.1): the run goes
+    through rupture onset (t ~ 820 for the noise film, ~ 130 with the Gaussian depression)."""
+    cfg = synth.CONFIGS[name]
+    g = Grid(cfg.n, cfg.n, cfg.ds)
+    g.set_model(10.0, 0.1, 3, 2)
+    g.set_scheme(**ADAPT)
+    g.set_diagnostics(True)
+    h = torch.from_numpy(cfg.film()).to(DEV)
+    g.bind(h)
+    m0, _ = g.mass()
+    dt, hmin = cfg.dt, 1.0
+    for _ in range(40):
+        dt, log = g.advance(50, dt, log=True)
+        for x in log:
+            assert abs(x["mass"] - m0) <= 1e-12 * m0
+            assert x["hmin"] > 0.0
+            hmin = min(hmin, x["hmin"])
+    assert hmin < 0.2
+    assert torch.isfinite(h).all()
