@@ -24,7 +24,8 @@ sys.path.insert(0, ROOT)
 METRIC = ("ADI steps/s & HBM GB/s (FP64, 2048²/8192²); ensemble + adjoint cost vs forward")
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per cell for each kernel class (one read of each input field and
-# one write of the output field of its sweep); see DESIGN.md "Roofline".
+# one write of the output field of its sweep; the y sweep reads u_k and b^n and writes w,
+# the x sweep reads u_k and w and writes u_{k+1}: 48 B per cell per Newton iteration).
 ALGO_BYTES_PER_CELL = {"relations_y": 16, "solve_y": 24, "relations_x": 16, "solve_x": 24}
 KERNEL_SOURCES = ["paper_1806_10550_amd/csrc/tf_kernels.hip", "paper_1806_10550_amd/csrc/tf_internal.h",
                   "paper_1806_10550_amd/csrc/tf_device.h"]

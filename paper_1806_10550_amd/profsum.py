@@ -84,19 +84,19 @@ def copy_duration_us(d, counter):
     return statistics.mean(durs) if durs else None
 
 
-# the counter runs this record summarises (repo root R on the GPU machine, run from /tmp with
-# TMPDIR=/tmp); one counter per pass
+# the counter runs this record summarises (R: the repository root, OUT: any output
+# directory; run from /tmp with TMPDIR=/tmp); one counter per pass
 COMMANDS = [
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_fetch -o run -- "
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_fetch -o run -- "
     "python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_write -o run -- "
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_write -o run -- "
     "python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/copy_fetch -o run -- "
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/copy_fetch -o run -- "
     "python $R/bench.py --calibrate-copy",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/copy_write -o run -- "
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/copy_write -o run -- "
     "python $R/bench.py --calibrate-copy",
-    "python -m paper_1806_10550_amd.profsum traffic --fetch gpurun_out/pmc_fetch --write gpurun_out/pmc_write "
-    "--copy-fetch gpurun_out/copy_fetch --copy-write gpurun_out/copy_write --copy-bytes 1073741824 "
+    "python -m paper_1806_10550_amd.profsum traffic --fetch $OUT/pmc_fetch --write $OUT/pmc_write "
+    "--copy-fetch $OUT/copy_fetch --copy-write $OUT/copy_write --copy-bytes 1073741824 "
     "--hash $(python bench.py --print-hash)",
 ]
 
@@ -140,11 +140,11 @@ def traffic(a):
 
 SQ_COMMANDS = [
     "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 "
-    "SQ_INSTS_VALU_ADD_F64 SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES --output-format csv -d $R/gpurun_out/pmc_sqa -o run -- "
+    "SQ_INSTS_VALU_ADD_F64 SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES --output-format csv -d $OUT/pmc_sqa -o run -- "
     "python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
     "rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_WAIT_INST_ANY SQ_INSTS_LDS SQ_ACTIVE_INST_LDS SQ_INSTS_SALU "
-    "--output-format csv -d $R/gpurun_out/pmc_sqb -o run -- python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-    "python -m paper_1806_10550_amd.profsum sq gpurun_out/pmc_sqa gpurun_out/pmc_sqb --hash $(python bench.py --print-hash)",
+    "--output-format csv -d $OUT/pmc_sqb -o run -- python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+    "python -m paper_1806_10550_amd.profsum sq $OUT/pmc_sqa $OUT/pmc_sqb --hash $(python bench.py --print-hash)",
 ]
 
 
