@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -91,10 +93,22 @@ def cpu_baseline(h_np, ds, dt, iters_per_step, model="power"):
     t0 = time.perf_counter()
     orc.adi_iteration(M, h_np, h_np, ds, dt, 1.0)
     t_it = time.perf_counter() - t0
-    return {"value": 1.0 / (t_it * iters_per_step), "unit": "steps/s", "cores": orc.get_threads(),
+    cores = orc.get_threads()
+    # one thread, on the top-left quarter by quarter of the film (1/16 of the cells), scaled
+    # by the cell count
+    sub = np.ascontiguousarray(h_np[: h_np.shape[0] // 4, : h_np.shape[1] // 4])
+    orc.set_threads(1)
+    t0 = time.perf_counter()
+    orc.adi_iteration(M, sub, sub, ds, dt, 1.0)
+    t_1 = (time.perf_counter() - t0) * (h_np.size / sub.size)
+    orc.set_threads(threads)
+    return {"value": 1.0 / (t_it * iters_per_step), "unit": "steps/s", "cores": cores,
             "kind": "oracle",
             "sample": (f"one Newton iteration on the full {h_np.shape[1]}x{h_np.shape[0]} film "
-                       f"({t_it:.2f} s), scaled by the GPU run's {iters_per_step:.2f} iterations/step")}
+                       f"({t_it:.2f} s), scaled by the GPU run's {iters_per_step:.2f} iterations/step"),
+            "single_thread_value": 1.0 / (t_1 * iters_per_step),
+            "single_thread_sample": (f"one Newton iteration on {sub.shape[1]}x{sub.shape[0]} cells of the same "
+                                     f"film on one thread, scaled to the full film ({t_1:.1f} s per iteration)")}
 
 
 def bench_ensemble(args):
