@@ -116,3 +116,11 @@ def test_second_order_in_time_and_space(orc, kind, h0):
         idx = m * np.arange(36 * 3 ** k) + (m - 1) // 2
         e.append(np.sqrt(np.mean((sols[k] - sols[-1][np.ix_(idx, idx)]) ** 2)))
     assert 1.9 <= math.log(e[1] / e[2], 3) <= 2.2, e
+
+
+def test_nlc_dimensional_wavelength(orc):
+    """Sec. "Comparison to Experimental Results": the most unstable wavelength of the NLC film
+    is 42 um with the scales of eq. NLC_scales (L = 10 um) and the parameters of eq.
+    NLC_paras; H0 = 0.5 (the NLC thickness of Sec. "Validation") gives 2 pi / q_m = 4.24."""
+    qm, _ = lsa(orc, orc.Model.nlc(), 0.5)
+    assert round(2 * math.pi / qm * 10.0) == 42
