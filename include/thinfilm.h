@@ -156,8 +156,9 @@ const char *tf_profile_names(void);
  * Many independent films (different sizes, kappa and ds; common b, n, m) advanced in
  * lockstep: one Newton iteration of every film that is still iterating is one replay of
  * a captured HIP graph; each film's Newton / dt control (Fig. FlowChartTime) runs on the
- * device, so converged films drop out while the others continue. Backward Euler only.
- * The films' states live in ONE packed device buffer: film f occupies nx[f]*ny[f]
+ * device, so converged films drop out while the others continue. With theta < 1 each film's
+ * b^n = u^n - (1 - theta) dt D(u^n) is formed on the device at the first iteration of every
+ * attempt (eq. TrapRule in theta form), as the single-film path does. The films' states live in ONE packed device buffer: film f occupies nx[f]*ny[f]
  * row-major doubles starting at offsets[f] (tf_ensemble_offsets), films back to back in
  * the order given. Work is done on an internal stream ordered after `stream`. */
 typedef struct tf_ensemble tf_ensemble;
@@ -172,7 +173,7 @@ tf_status tf_ensemble_set_model_linear(tf_ensemble *e, double c0, double c1);
 tf_status tf_ensemble_set_model_nlc(tf_ensemble *e, double C, double K, double N, double beta, double w, double b);
 tf_status tf_ensemble_set_model_polymer(tf_ensemble *e, double C, double Cst, double Aox, double Asi, double d);
 tf_status tf_ensemble_destroy(tf_ensemble *e);
-/* scheme as for tf_set_scheme; theta must be 1 (TF_EINVAL otherwise) */
+/* scheme as for tf_set_scheme (theta in [0.5, 1]; theta < 1 allocates one packed field) */
 tf_status tf_ensemble_set_scheme(tf_ensemble *e, const tf_scheme *s);
 /* total number of cells (length of the packed buffer) */
 long long tf_ensemble_size(const tf_ensemble *e);

@@ -49,6 +49,7 @@ struct tf_ensemble {
     int *d_active = nullptr, *h_active = nullptr;
     double *buf0 = nullptr, *buf1 = nullptr, *buf2 = nullptr, *w = nullptr;
     double *rel = nullptr, *ext = nullptr, *chain = nullptr;
+    double *bn = nullptr;  // packed b^n (allocated when a scheme with theta < 1 is set)
     int km = tf::KM_P32; // model form of the sweep kernels (one model for every film)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -69,6 +70,7 @@ tf::EnsParams params(const tf_ensemble *e, int which)
     p.rel = e->rel;
     p.ext = e->ext;
     p.chain = e->chain;
+    p.bn = e->bn;
     p.theta = e->S.theta;
     const int off_y = 0, off_x = 3 * e->ny_items, off_cy = off_x + 3 * e->nx_items, off_cx = off_cy + 2 * e->ncy_items;
     switch (which) {
@@ -84,6 +86,7 @@ tf_status enqueue_iteration(tf_ensemble *e)
 {
     const tf::EnsScheme S{e->S.theta, e->S.tol, e->S.dt_min, e->S.dt_max, e->S.dt_shrink, e->S.dt_grow,
                           e->S.max_newton, e->S.grow_after, e->S.adaptive};
+    if (e->S.theta < 1.0) TF_EHIP(tf::launch_bn_ens(params(e, 0), e->stream));
     TF_EHIP(tf::launch_pass_ens(0, false, e->km, params(e, 0), e->stream));
     TF_EHIP(tf::launch_chain_ens(params(e, 2), 0, e->stream));
     TF_EHIP(tf::launch_pass_ens(0, true, e->km, params(e, 0), e->stream));
@@ -247,6 +250,7 @@ tf_status tf_ensemble_destroy(tf_ensemble *e)
     (void)hipFree(e->rel);
     (void)hipFree(e->ext);
     (void)hipFree(e->chain);
+    (void)hipFree(e->bn);
     if (e->h_state) (void)hipHostFree(e->h_state);
     if (e->h_active) (void)hipHostFree(e->h_active);
     if (e->stream) (void)hipStreamDestroy(e->stream);
@@ -266,11 +270,17 @@ tf_status tf_ensemble_offsets(const tf_ensemble *e, long long *offsets)
 tf_status tf_ensemble_set_scheme(tf_ensemble *e, const tf_scheme *s)
 {
     if (e == nullptr || s == nullptr) return efail(TF_EINVAL, "NULL argument");
-    if (s->theta != 1.0) return efail(TF_EINVAL, "the ensemble path runs backward Euler (theta = 1)");
+    if (!(s->theta >= 0.5 && s->theta <= 1.0)) return efail(TF_EINVAL, "theta must lie in [0.5, 1]");
     if (!(s->tol > 0.0) || s->max_newton < 1) return efail(TF_EINVAL, "need tol > 0 and max_newton >= 1");
     if (s->adaptive && (!(s->dt_shrink > 0.0 && s->dt_shrink < 1.0) || !(s->dt_grow >= 1.0) || !(s->dt_min > 0.0)
                         || !(s->dt_max >= s->dt_min) || s->grow_after < 1))
         return efail(TF_EINVAL, "inconsistent adaptive-dt parameters");
+    if (s->theta < 1.0 && e->bn == nullptr) {
+        if (hipMalloc(&e->bn, (size_t)e->ncells * sizeof(double)) != hipSuccess) {
+            e->bn = nullptr;
+            return efail(TF_ENOMEM, "device allocation failed");
+        }
+    }
     e->S = *s;
     drop_graph(e);
     return TF_OK;

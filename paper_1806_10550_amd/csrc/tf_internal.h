@@ -125,6 +125,7 @@ struct EnsParams {
     int nitems;
     double *buf0, *buf1, *buf2; // packed u buffers; index 0 is the caller's state
     double *w, *rel, *ext, *chain;
+    double *bn;            // packed b^n = u^n - (1 - theta) dt D(u^n) (theta < 1 only)
     double theta;
 };
 enum ResultFlag { FLAG_NONPOS = 1, FLAG_NAN = 2 };
@@ -141,6 +142,8 @@ hipError_t launch_flux_divergence(int nx, int ny, double ids, double ids2, const
                                   double *out, hipStream_t s);
 hipError_t launch_mass(const double *u, size_t n, double *partials, int nblocks, hipStream_t s);
 hipError_t launch_pass_ens(int dir, bool solve, int km, const EnsParams &e, hipStream_t s);
+// b^n of every active film at the first iteration of an attempt (items: the y-sweep tiles)
+hipError_t launch_bn_ens(const EnsParams &e, hipStream_t s);
 hipError_t launch_chain_ens(const EnsParams &e, int dir, hipStream_t s);
 hipError_t launch_ens_control(FilmState *st, int nfilms, const EnsScheme &S, int *active_count, hipStream_t s);
 hipError_t launch_ens_begin(FilmState *st, int nfilms, hipStream_t s);

@@ -543,7 +543,7 @@ __global__ void TF_PASS_ATTR k_pass_ens(EnsParams e)
     p.K1 = p.ka * d.M.Dn;
     p.M = d.M;
     p.u = B[s->it] + d.off;
-    p.in2 = DIR == 0 ? B[s->cur] + d.off : e.w + d.off;
+    p.in2 = DIR == 0 ? (e.theta < 1.0 ? e.bn : B[s->cur]) + d.off : e.w + d.off;
     p.out = DIR == 0 ? e.w + d.off : B[s->nxt] + d.off;
     p.rel = e.rel + d.roff * NREL;
     p.ext = e.ext + d.roff * NEXT;
@@ -815,14 +815,12 @@ __device__ __forceinline__ void cell_g(const double *u, int nx, int ny, int i, i
     model_coefs<P32>(M, uc, f0, f1, f0p, f1p);
 }
 
+// D(u) at cell (i, j): the flux differences of eq. GovEqnCell2 with zero boundary fluxes
+// (NOF0: the f1 part only).
 template <bool P32, bool NOF0>
-__global__ void __launch_bounds__(256) k_flux_divergence(int nx, int ny, double ids, double ids2, Model M,
-                                                         const double *u, double alpha, double beta,
-                                                         const double *add, double *out)
+__device__ __forceinline__ double flux_div_at(const double *u, int nx, int ny, int i, int j, double ids, double ids2,
+                                              const Model &M)
 {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= nx || j >= ny) return;
     double uc, lc, f0c, f1c;
     cell_g<P32>(u, nx, ny, i, j, M, ids2, uc, lc, f0c, f1c);
     double F[4];
@@ -840,9 +838,47 @@ __global__ void __launch_bounds__(256) k_flux_divergence(int nx, int ny, double 
         const double du = lower ? (uc - un) : (un - uc);
         F[k] = inside[k] ? A * (dl * ids) + B * (du * ids) : 0.0;
     }
-    const double D = (F[1] - F[0] + F[3] - F[2]) * ids;
+    return (F[1] - F[0] + F[3] - F[2]) * ids;
+}
+
+template <bool P32, bool NOF0>
+__global__ void __launch_bounds__(256) k_flux_divergence(int nx, int ny, double ids, double ids2, Model M,
+                                                         const double *u, double alpha, double beta,
+                                                         const double *add, double *out)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= nx || j >= ny) return;
+    const double D = flux_div_at<P32, NOF0>(u, nx, ny, i, j, ids, ids2, M);
     const size_t o = (size_t)j * nx + i;
     out[o] = (add != nullptr ? alpha * add[o] : 0.0) + beta * D;
+}
+
+// Ensemble b^n = u^n - (1 - theta) dt D(u^n), block -> one y-sweep tile (LT0 columns x one
+// segment of rows) of a film that is active and at the first iteration of its attempt (the
+// same arithmetic as k_flux_divergence with alpha = 1, so the ensemble matches the single film).
+__global__ void __launch_bounds__(256) k_bn_ens(EnsParams e)
+{
+    const int t = xcd_tile(blockIdx.x, e.nitems);
+    const int f = e.items[3 * t], tx = e.items[3 * t + 1], ty = e.items[3 * t + 2];
+    const FilmState *s = e.state + f;
+    if (!s->active || s->k != 0) return;
+    const FilmDesc d = e.desc[f];
+    const double *B[3] = {e.buf0, e.buf1, e.buf2};
+    const double *un = B[s->cur] + d.off;
+    double *bn = e.bn + d.off;
+    const double ids = 1.0 / d.ds, ids2 = ids * ids;
+    const double beta = -(1.0 - e.theta) * s->dt;
+    const int i0 = tx * LT0, i1 = min(i0 + LT0, d.nx);
+    const int j0 = seg_start(ty, d.ny), j1 = seg_start(ty + 1, d.ny);
+    const int w = i1 - i0;
+    for (int c = threadIdx.x; c < w * (j1 - j0); c += 256) {
+        const int i = i0 + c % w, j = j0 + c / w;
+        const double D = d.M.p32 ? flux_div_at<true, false>(un, d.nx, d.ny, i, j, ids, ids2, d.M)
+                                 : flux_div_at<false, false>(un, d.nx, d.ny, i, j, ids, ids2, d.M);
+        const size_t o = (size_t)j * d.nx + i;
+        bn[o] = un[o] + beta * D; // fma(beta, D, u), as in k_flux_divergence
+    }
 }
 
 // ------------------------------------------------------------------------------------
@@ -1125,6 +1161,12 @@ hipError_t launch_pass_ens(int dir, bool solve, int km, const EnsParams &e, hipS
     case KM_NLC: launch_pass_ens_km<KM_NLC>(dir, solve, e, s); break;
     default: launch_pass_ens_km<KM_POLYMER>(dir, solve, e, s); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_bn_ens(const EnsParams &e, hipStream_t s)
+{
+    k_bn_ens<<<dim3(e.nitems), dim3(256), 0, s>>>(e);
     return hipGetLastError();
 }
 

@@ -274,7 +274,7 @@ class Grid:
 
 class Ensemble:
     """Films of different sizes / kappa / ds packed in one buffer and stepped in lockstep
-    (include/thinfilm.h, tf_ensemble_*). Backward Euler only."""
+    (include/thinfilm.h, tf_ensemble_*); theta scheme with theta in [0.5, 1]."""
 
     def __init__(self, nx, ny, ds, kappa, b=0.1, n=3, m=2, stream=None):
         k = len(nx)

@@ -156,3 +156,30 @@ def test_model_ensemble_rejects_bad_parameters():
         ens.set_model_polymer(C=-1.0)
     with pytest.raises(TFError):
         ens.set_model_linear(c0=0.0)
+
+
+@pytest.mark.parametrize("adaptive,dt0", [(0, 0.1), (1, 2.0)])
+def test_theta_half_ensemble_equals_single_film_path_bitwise(adaptive, dt0):
+    """The trapezoidal rule (theta = 1/2, eq. TrapRule) in the ensemble: b^n is formed on the
+    device at the first iteration of each attempt; with adaptive steps from dt = 2 the films
+    reject and retry with smaller dt. Every film ends bit for bit where it ends alone, with the
+    same dt and iteration count."""
+    nx, ny, kap, ds, h0 = films_setup(FILMS[:5])
+    kw = dict(theta=0.5, tol=1e-10, max_newton=10 if adaptive else 5000, adaptive=adaptive, dt_min=1e-6,
+              dt_max=4.0, dt_shrink=0.5, dt_grow=1.1, grow_after=5)
+    ens = Ensemble(nx, ny, ds, kap)
+    ens.set_scheme(**kw)
+    packed = pack(ens, h0)
+    ens.bind(packed)
+    st, dts, sts, its = ens.step(6, dt0)
+    assert st == TF_OK and all(s == TF_OK for s in sts)
+    rejected = 0
+    for f in range(5):
+        s1, dtn, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 6, dt0, **kw)
+        assert s1 == TF_OK
+        assert dts[f] == dtn
+        assert its[f] == sum(x["total_iters"] for x in log)
+        assert torch.equal(ens.view(packed, f), h), f
+        rejected += sum(x["rejections"] for x in log)
+    if adaptive:
+        assert rejected > 0  # the retry path (b^n recomputed with the shrunk dt) was exercised
