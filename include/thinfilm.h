@@ -122,6 +122,14 @@ tf_status tf_set_diagnostics(tf_grid *g, int mass_every_step);
  * in place; during a call it may also hold iterates there. It must stay allocated
  * until unbound (tf_bind_state(g, NULL)) or tf_destroy. Resets the time to 0. */
 tf_status tf_bind_state(tf_grid *g, double *h_dev);
+/* The clock of the bound state (host scalars): time t and the number of consecutive accepted
+ * steps that count towards the next dt growth of the adaptive control (Fig. FlowChartTime).
+ * With the state itself and the dt proposed for the next step, it is all a later run needs to
+ * continue exactly where this one stopped (checkpoint / resume): bind the saved state, set
+ * the clock, step with the saved dt. tf_set_clock: TF_EINVAL for non-finite t or
+ * successes < 0; call it after tf_bind_state, which resets the clock. */
+tf_status tf_get_clock(const tf_grid *g, double *t, int *successes);
+tf_status tf_set_clock(tf_grid *g, double t, int successes);
 
 /* Advance the bound state by exactly one accepted step. *dt_inout: dt to try in,
  * dt for the next step out. info may be NULL. TF_ENONPOS if the state holds h <= 0

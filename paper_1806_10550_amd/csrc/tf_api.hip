@@ -586,6 +586,23 @@ tf_status tf_bind_state(tf_grid *g, double *h_dev)
     return TF_OK;
 }
 
+tf_status tf_get_clock(const tf_grid *g, double *t, int *successes)
+{
+    if (g == nullptr || t == nullptr || successes == nullptr) return fail(TF_EINVAL, "NULL argument");
+    *t = g->t;
+    *successes = g->successes;
+    return TF_OK;
+}
+
+tf_status tf_set_clock(tf_grid *g, double t, int successes)
+{
+    if (g == nullptr) return fail(TF_EINVAL, "grid is NULL");
+    if (!std::isfinite(t) || successes < 0) return fail(TF_EINVAL, "need finite t and successes >= 0");
+    g->t = t;
+    g->successes = successes;
+    return TF_OK;
+}
+
 tf_status tf_step(tf_grid *g, double *dt_inout, tf_step_info *info)
 {
     if (g == nullptr || dt_inout == nullptr) return fail(TF_EINVAL, "NULL argument");

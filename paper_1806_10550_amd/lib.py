@@ -60,6 +60,8 @@ def lib():
         L.tf_destroy.argtypes = [P]
         L.tf_set_model.argtypes = [P, D, D, D, D]
         L.tf_set_model_linear.argtypes = [P, D, D]
+        L.tf_get_clock.argtypes = [P, C.POINTER(D), C.POINTER(C.c_int)]
+        L.tf_set_clock.argtypes = [P, D, C.c_int]
         L.tf_radial_spectrum.argtypes = [P, C.c_int, D, D, D, D, P, P, P, P, C.c_int, P]
         L.tf_spectrum_maxima.argtypes = [P, P, C.c_int, D, C.c_int, P, P, P, C.c_int, P]
         L.tf_model_coeffs.argtypes = [P, P, C.c_int, P]
@@ -207,6 +209,30 @@ class Grid:
         info = StepInfo()
         _check(lib().tf_step(self._h, C.byref(d), C.byref(info)))
         return StepResult(d.value, info.as_dict())
+
+    def clock(self):
+        """(t, successes) of the bound state (tf_get_clock)."""
+        t, s = C.c_double(), C.c_int()
+        _check(lib().tf_get_clock(self._h, C.byref(t), C.byref(s)))
+        return t.value, s.value
+
+    def set_clock(self, t: float, successes: int):
+        _check(lib().tf_set_clock(self._h, float(t), int(successes)))
+        return self
+
+    def checkpoint(self, dt_next: float) -> dict:
+        """What a later run needs to continue this one exactly: a host copy of the state,
+        its clock and the dt to try next (a dict of tensors and numbers, torch.save-able)."""
+        t, s = self.clock()
+        return {"h": self._state.detach().cpu().clone(), "t": t, "successes": s, "dt": float(dt_next)}
+
+    def restore(self, ckpt: dict, h):
+        """Copy a checkpoint's state into h (a (ny, nx) float64 CUDA tensor), bind it, set
+        the clock; returns the dt to try next."""
+        h.copy_(ckpt["h"])
+        self.bind(h)
+        self.set_clock(ckpt["t"], ckpt["successes"])
+        return ckpt["dt"]
 
     def advance(self, nsteps: int, dt: float, log: bool = False):
         d = C.c_double(dt)

@@ -76,3 +76,10 @@ def test_autotune_arguments_and_default_choice(L, tmp_path):
     # nothing tuned in this process: partitioned below 65536 lines, Thomas from there on
     assert L.tf_autotune_choice(512, 512, 1) == 0
     assert L.tf_autotune_choice(128, 65536, 0) == 1
+
+
+def test_clock_arguments(L):
+    L.tf_set_clock.argtypes = [C.c_void_p, C.c_double, C.c_int]
+    L.tf_get_clock.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    assert L.tf_set_clock(None, 0.0, 0) == TF_EINVAL
+    assert L.tf_get_clock(None, None, None) == TF_EINVAL

@@ -196,3 +196,26 @@ def test_adaptive_schedule_matches_oracle(orc):
         assert log[s]["rejections"] == res.rejections
         dto, succ = res.dt_next, res.successes
     assert np.max(np.abs(h.cpu().numpy() - u) / u) <= 1e-10
+
+
+def test_checkpoint_resume_is_exact():
+    """Checkpoint / resume: 6 adaptive steps, a checkpoint (state, clock, next dt), 6 more
+    steps; a fresh grid restored from the checkpoint reaches the same state bit for bit, with
+    the same time and the same next dt (the success counter carries the dt growth)."""
+    kw = dict(tol=1e-10, max_newton=10, adaptive=1, dt_min=1e-6, dt_max=1.0, dt_shrink=0.5, dt_grow=1.1,
+              grow_after=5)
+    nx, ny, ds = 70, 66, 0.67347
+    h0 = synth.noise_film(nx, ny, seed=21, amp=0.01)
+    g = make_grid(nx, ny, ds, **kw)
+    h = gpu(h0)
+    g.bind(h)
+    dt, _ = g.advance(6, 0.1)
+    ck = g.checkpoint(dt)
+    dt_a, _ = g.advance(6, dt)
+    t_a = g.clock()[0]
+    g2 = make_grid(nx, ny, ds, **kw)
+    h2 = torch.empty_like(h)
+    dt2 = g2.restore(ck, h2)
+    dt_b, _ = g2.advance(6, dt2)
+    assert torch.equal(h, h2)
+    assert dt_a == dt_b and g2.clock()[0] == t_a
