@@ -83,3 +83,34 @@ def test_clock_arguments(L):
     L.tf_get_clock.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     assert L.tf_set_clock(None, 0.0, 0) == TF_EINVAL
     assert L.tf_get_clock(None, None, None) == TF_EINVAL
+
+
+def test_model_entry_points_reject_null_handles(L):
+    D = C.c_double
+    L.tf_set_model_linear.argtypes = [C.c_void_p, D, D]
+    L.tf_set_model_nlc.argtypes = [C.c_void_p, D, D, D, D, D, D]
+    L.tf_set_model_polymer.argtypes = [C.c_void_p, D, D, D, D, D]
+    L.tf_ensemble_set_model_nlc.argtypes = [C.c_void_p, D, D, D, D, D, D]
+    L.tf_ensemble_set_model_polymer.argtypes = [C.c_void_p, D, D, D, D, D]
+    L.tf_ensemble_set_model_linear.argtypes = [C.c_void_p, D, D]
+    L.tf_model_coeffs.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    assert L.tf_set_model_linear(None, 1.0, 1.0) == TF_EINVAL
+    assert L.tf_set_model_nlc(None, 0.0857, 36.0, 1.67, 1.0, 0.05, 0.01) == TF_EINVAL
+    assert L.tf_set_model_polymer(None, 0.00581, 1.181, 41.25, -243.75, 191.0) == TF_EINVAL
+    assert L.tf_ensemble_set_model_linear(None, 1.0, 1.0) == TF_EINVAL
+    assert L.tf_ensemble_set_model_nlc(None, 0.0857, 36.0, 1.67, 1.0, 0.05, 0.01) == TF_EINVAL
+    assert L.tf_ensemble_set_model_polymer(None, 0.00581, 1.181, 41.25, -243.75, 191.0) == TF_EINVAL
+    assert L.tf_model_coeffs(None, None, 1, None) == TF_EINVAL
+
+
+def test_radial_spectrum_validates_before_any_device_work(L):
+    D = C.c_double
+    L.tf_radial_spectrum.argtypes = [C.c_void_p, C.c_int, D, D, D, D, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_int, C.c_void_p]
+    n = C.c_int(0)
+    p = C.c_void_p(16)  # never dereferenced: validation fails first
+    assert L.tf_radial_spectrum(None, 64, 0.1, 1.0, 1.0, 1.0, None, None, None, None, 0, C.byref(n)) == TF_EINVAL
+    assert L.tf_radial_spectrum(p, 2, 0.1, 1.0, 1.0, 1.0, None, None, None, None, 0, C.byref(n)) == TF_EINVAL
+    assert L.tf_radial_spectrum(p, 64, -0.1, 1.0, 1.0, 1.0, None, None, None, None, 0, C.byref(n)) == TF_EINVAL
+    assert L.tf_radial_spectrum(p, 64, 0.1, 1.0, -1.0, 1.0, None, None, None, None, 0, C.byref(n)) == TF_EINVAL
+    assert L.tf_radial_spectrum(p, 64, 0.1, 1.0, 1.0, float("nan"), None, None, None, None, 0, C.byref(n)) == TF_EINVAL
