@@ -1,0 +1,53 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU guard and that the committed
+profiles were taken on the kernel sources in the tree."""
+import json
+import os
+import re
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_print_hash_matches_kernel_sources():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--print-hash"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0
+    assert r.stdout.strip() == bench.kernel_hash()
+
+
+def test_committed_profiles_match_kernel_sources():
+    """The traffic and SQ counter summaries and the kernel trace carry the hash of the kernel
+    sources they were taken on; bench.py reports null traffic once they differ."""
+    h = bench.kernel_hash()
+    for name in ("traffic_large8192.json", "sq_large8192.json"):
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            assert json.load(f)["kernel_hash"] == h, name
+    with open(os.path.join(ROOT, "profiles", "tile_kernels_large8192_ktrace.txt")) as f:
+        m = re.search(r"kernel sources hash ([0-9a-f]{16})", f.read())
+    assert m and m.group(1) == h
+
+
+def test_counter_summaries_are_usable():
+    """Every tile kernel class has fetch and write bytes per dispatch, and the dominant kernel has
+    an FP64 flop count (the counter is per wave instruction: 64 lanes each)."""
+    with open(bench.TRAFFIC_FILE) as f:
+        t = json.load(f)
+    for k in bench.ALGO_BYTES_PER_CELL:
+        rec = t["kernels"][k]
+        assert rec["fetch_kib"] > 0 and rec["write_kib"] > 0 and rec["dispatches"] > 0
+        # counter traffic is never below the algorithmic bytes of an 8192^2 launch
+        algo_kib = bench.ALGO_BYTES_PER_CELL[k] * 8192 * 8192 / 1024
+        assert rec["fetch_kib"] + rec["write_kib"] >= algo_kib, k
+    flops = bench.fp64_flops_for("solve_x")
+    assert flops is not None and flops > 100 * 8192 * 8192
