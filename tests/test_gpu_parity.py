@@ -245,3 +245,49 @@ def test_step_commutes_with_reflections(nx, ny):
     if nx == ny:
         assert np.max(np.abs(step(u.T).T - v)) <= 1e-10 * scale
     assert abs(v.sum() - u.sum()) <= 1e-13 * u.sum()
+
+
+def test_nucleation_film_through_the_horizon_matches_oracle_replay(orc):
+    """A 320^2 film (L = 10 lambda_m, the benchmark spacing) with a Gaussian depression of depth
+    0.3 and width lambda_m / 4 at the centre over noise 0.01 (seed 1), adaptive dt from 0.1
+    with K = 10, run on the GPU until min h falls below 0.5 (the pre-rupture horizon, about
+    470 steps and 3100 Newton iterations to t ~ 60). The oracle replays the GPU's schedule:
+    each accepted step from u^n with the same dt and the same number of Newton iterations.
+    Every 20 steps h agrees to 1e-10 relative; the oracle's own convergence test takes the
+    same accept decision at (nearly) every step; mass is conserved to 1e-12."""
+    cfg = synth.FilmConfig("nucleation320", 320, 10.0, seed=1, dt=0.1, adaptive=1,
+                           extra={"gaussian": True, "depth": 0.3})
+    kw = dict(tol=1e-10, max_newton=10, adaptive=1, dt_min=1e-6, dt_max=1.0, dt_shrink=0.5, dt_grow=1.1,
+              grow_after=5)
+    h0 = cfg.film()
+    g = make_grid(cfg.n, cfg.n, cfg.ds, **kw)
+    g.set_diagnostics(True)
+    h = gpu(h0)
+    g.bind(h)
+    m0, _ = g.mass()
+    dt, logs, snaps = cfg.dt, [], []
+    while len(logs) < 800:
+        dt, log = g.advance(20, dt, log=True)
+        logs += log
+        for x in log:
+            assert abs(x["mass"] - m0) <= 1e-12 * m0
+        if log[-1]["hmin"] < 0.5:
+            break
+        snaps.append((len(logs), h.cpu().numpy()))
+    assert logs[-1]["hmin"] < 0.5 and len(snaps) >= 15
+    assert any(x["rejections"] > 0 for x in logs)
+
+    M = omodel(orc)
+    u, disagree = h0, 0
+    checks = dict(snaps)
+    for s, x in enumerate(logs[:snaps[-1][0]]):
+        uk = u
+        for k in range(x["newton_iters"]):
+            uk, e, _ = orc.adi_iteration(M, u, uk, cfg.ds, x["dt_used"], 1.0)
+            if (e < kw["tol"]) != (k == x["newton_iters"] - 1):
+                disagree += 1
+        u = uk
+        if s + 1 in checks:
+            rel = np.max(np.abs(checks[s + 1] - u) / u)
+            assert rel <= 1e-10, (s + 1, rel)
+    assert disagree <= 3, disagree
