@@ -191,6 +191,36 @@ def test_rollout_gradient_matches_oracle_adjoint(orc):
     assert kap.grad.item() == pytest.approx(gk, rel=1e-8)
 
 
+def test_full_size_rollout_gradient_matches_finite_differences():
+    """The 512^2 adjoint workload as timed (L = 16 lambda_m, 400 backward-Euler steps of dt = 0.1,
+    checkpoints every 20, p0 = 0 on the seed-4 film, target = the seed-5 film run forward over the
+    same 400 steps, loss 0.5 ||h(T) - target||^2), with forward and adjoint tolerances 1e-12: the
+    directional derivatives in p0 (random direction) and kappa match central differences with
+    step 1e-4 to 1e-5 relative (differences of the loss carry the forward tolerance over the
+    step, ~1e-8 relative; the truncation error is O(step^2))."""
+    cfg = synth.CONFIGS["adjoint512"]
+    n, dt, steps, ds, ck = cfg.n, cfg.dt, cfg.steps, cfg.ds, cfg.extra["checkpoint_every"]
+    tol = 1e-12
+    base = gpu(synth.noise_film(n, n, cfg.seed, 1.0, 0.01))
+    tgt = gpu(synth.noise_film(n, n, cfg.extra["target_seed"], 1.0, 0.01))
+    g = grid(n, n, ds, tol=tol, max_newton=5000)
+    g.bind(tgt)
+    g.advance(steps, dt)
+    p0 = torch.zeros_like(base, requires_grad=True)
+    kap = torch.tensor(cfg.kappa, dtype=torch.float64, device=DEV, requires_grad=True)
+    h = rollout(p0, kap, base, steps, dt, ds, checkpoint_every=ck, tol=tol, adj_tol=tol)
+    _loss(h, tgt).backward()
+    d = gpu(np.random.default_rng(7).standard_normal((n, n)))
+    eps = 1e-4
+    with torch.no_grad():
+        Lp = _loss(rollout(p0 + eps * d, kap, base, steps, dt, ds, tol=tol), tgt).item()
+        Lm = _loss(rollout(p0 - eps * d, kap, base, steps, dt, ds, tol=tol), tgt).item()
+        assert torch.sum(p0.grad * d).item() == pytest.approx((Lp - Lm) / (2 * eps), rel=1e-5)
+        Lp = _loss(rollout(p0, kap + eps, base, steps, dt, ds, tol=tol), tgt).item()
+        Lm = _loss(rollout(p0, kap - eps, base, steps, dt, ds, tol=tol), tgt).item()
+        assert kap.grad.item() == pytest.approx((Lp - Lm) / (2 * eps), rel=1e-5)
+
+
 def test_autotune_cache_roundtrip(tmp_path):
     path = str(tmp_path / "tune.jsonl")
     choice = autotune(512, 512, path)
