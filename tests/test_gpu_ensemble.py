@@ -183,3 +183,35 @@ def test_theta_half_ensemble_equals_single_film_path_bitwise(adaptive, dt0):
         rejected += sum(x["rejections"] for x in log)
     if adaptive:
         assert rejected > 0  # the retry path (b^n recomputed with the shrunk dt) was exercised
+
+
+def test_full_ensemble_matches_oracle_on_sampled_films(orc):
+    """The 256-film ensemble as timed (sizes {256..1024}^2, kappa ~ U[5, 20], L = 8 lambda_m,
+    noise 0.01 from default_rng(3); adaptive dt from 0.1, K = 10, tol 1e-10): after 3 steps,
+    8 films drawn by a seeded generator agree with the oracle's own adaptive run of the same
+    film to 1e-10 relative, with the same next dt."""
+    films = synth.ensemble_films(256)
+    nx = [f.n for f in films]
+    ds = [f.ds for f in films]
+    kap = [f.kappa for f in films]
+    h0 = [synth.noise_film(f.n, f.n, f.seed, 1.0, 0.01) for f in films]
+    scheme = dict(tol=1e-10, max_newton=10, adaptive=1, dt_min=1e-9, dt_max=1.0, dt_shrink=0.5, dt_grow=1.1,
+                  grow_after=5)
+    ens = Ensemble(nx, nx, ds, kap)
+    ens.set_scheme(**scheme)
+    packed = pack(ens, h0)
+    ens.bind(packed)
+    st, dts, sts, _ = ens.step(3, [0.1] * len(films))
+    assert st == TF_OK and all(s == TF_OK for s in sts)
+    pick = np.random.default_rng(11).choice(len(films), 8, replace=False)
+    S = orc.Scheme(theta=1.0, **scheme)
+    for f in pick:
+        M = orc.Model(kappa=kap[f], b=0.1, n=3.0, m=2.0)
+        u, dt, succ = h0[f], 0.1, 0
+        for _ in range(3):
+            u, res = orc.step(M, S, u, ds[f], dt, succ)
+            assert res.status == orc.OK
+            dt, succ = res.dt_next, res.successes
+        got = ens.view(packed, int(f)).cpu().numpy()
+        assert np.max(np.abs(got - u) / u) <= 1e-10, f
+        assert dts[f] == dt, f
