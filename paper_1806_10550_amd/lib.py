@@ -261,13 +261,22 @@ class Grid:
         _check(lib().tf_mass(self._h, C.byref(m), C.byref(hm)))
         return m.value, hm.value
 
+    def _fields(self, *ts):
+        """The C calls take bare device pointers to (ny, nx) fields: check the shapes here,
+        before any device access."""
+        for t in ts:
+            if tuple(t.shape) != (self.ny, self.nx):
+                raise ValueError(f"fields must have shape ({self.ny}, {self.nx}), got {tuple(t.shape)}")
+
     def newton_iteration(self, un, uk, out, dt: float):
+        self._fields(un, uk, out)
         e, r, f = C.c_double(), C.c_double(), C.c_int()
         _check(lib().tf_newton_iteration(self._h, _ptr(un), _ptr(uk), _ptr(out), float(dt),
                                          C.byref(e), C.byref(r), C.byref(f)))
         return e.value, r.value, f.value
 
     def flux_divergence(self, u, out):
+        self._fields(u, out)
         _check(lib().tf_flux_divergence(self._h, _ptr(u), _ptr(out)))
         return out
 
@@ -276,6 +285,7 @@ class Grid:
         """lam (device, in/out): lambda^{n+1} -> lambda^n. Returns (dL/dkappa contribution,
         Richardson iterations); the contribution is None with dkappa=False (required for the
         NLC and polymer models, which have no kappa)."""
+        self._fields(h_n, h_np1, lam)
         g = C.c_double(0.0)
         it = C.c_int(0)
         _check(lib().tf_adjoint_step(self._h, _ptr(h_n), _ptr(h_np1), float(dt), _ptr(lam),
@@ -283,6 +293,7 @@ class Grid:
         return (g.value if dkappa else None), it.value
 
     def jacobian_apply_t(self, u, mu, out):
+        self._fields(u, mu, out)
         _check(lib().tf_jacobian_apply_t(self._h, _ptr(u), _ptr(mu), _ptr(out)))
         return out
 

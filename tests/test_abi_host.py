@@ -114,3 +114,23 @@ def test_radial_spectrum_validates_before_any_device_work(L):
     assert L.tf_radial_spectrum(p, 64, -0.1, 1.0, 1.0, 1.0, None, None, None, None, 0, C.byref(n)) == TF_EINVAL
     assert L.tf_radial_spectrum(p, 64, 0.1, 1.0, -1.0, 1.0, None, None, None, None, 0, C.byref(n)) == TF_EINVAL
     assert L.tf_radial_spectrum(p, 64, 0.1, 1.0, 1.0, float("nan"), None, None, None, None, 0, C.byref(n)) == TF_EINVAL
+
+
+def test_binding_checks_field_shapes_before_any_device_call():
+    """The C calls take bare pointers to (ny, nx) fields; the Python binding rejects a
+    field of another shape before it reaches the library."""
+    import torch
+
+    from paper_1806_10550_amd.lib import Grid
+    g = object.__new__(Grid)        # no device handle: the check must fire first
+    g._h, g.nx, g.ny = None, 8, 6
+    good = torch.zeros((6, 8), dtype=torch.float64)
+    bad = torch.zeros((8, 6), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        g.newton_iteration(good, good, bad, 0.1)
+    with pytest.raises(ValueError):
+        g.flux_divergence(bad, good)
+    with pytest.raises(ValueError):
+        g.adjoint_step(good, bad, 0.1, good)
+    with pytest.raises(ValueError):
+        g.jacobian_apply_t(good, good, torch.zeros(48, dtype=torch.float64))
