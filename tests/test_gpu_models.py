@@ -208,3 +208,28 @@ def test_set_model_validation():
         g.set_model_linear(c0=0.0)
     with pytest.raises(TFError):
         g.set_model_linear(c1=float("inf"))
+
+
+@pytest.mark.parametrize("kind,lo,hi", [("power", 0.12, 5.0), ("power52", 0.12, 5.0), ("linear", 0.1, 10.0),
+                                        ("nlc", 0.05, 3.0), ("polymer", 1.0, 40.0)])
+def test_model_coeffs_match_oracle(orc, kind, lo, hi):
+    """tf_model_coeffs (the sweeps' device code for f0, f0', f1, f1') against the oracle's
+    coefficients of eq. GeneralDisPreForm at 301 thicknesses spanning the model's range:
+    each coefficient to 1e-12 of its largest magnitude over the range."""
+    g = Grid(8, 8, 1.0)
+    if kind == "power":
+        g.set_model(10.0, 0.1, 3, 2)
+        M = orc.Model(kappa=10.0, b=0.1, n=3.0, m=2.0)
+    elif kind == "power52":
+        g.set_model(10.0, 0.1, 5, 2)
+        M = orc.Model(kappa=10.0, b=0.1, n=5.0, m=2.0)
+    else:
+        getattr(g, "set_model_" + kind)()
+        M = omodel(orc, kind)
+    h = np.geomspace(lo, hi, 301)
+    out = torch.empty((h.size, 4), dtype=torch.float64, device=DEV)
+    g.model_coeffs(gpu(h), out)
+    got = out.cpu().numpy()
+    ref = np.array([orc.coeffs(M, x) for x in h])
+    scale = np.max(np.abs(ref), axis=0)
+    assert np.all(np.abs(got - ref) <= 1e-12 * scale), np.max(np.abs(got - ref) / scale, axis=0)
