@@ -291,3 +291,20 @@ def test_nucleation_film_through_the_horizon_matches_oracle_replay(orc):
             rel = np.max(np.abs(checks[s + 1] - u) / u)
             assert rel <= 1e-10, (s + 1, rel)
     assert disagree <= 3, disagree
+
+
+def test_zero_and_negative_step_counts():
+    """advance(0) leaves the state and dt as they are (also after steps were taken);
+    a negative count is rejected."""
+    g = make_grid(37, 23, 0.67)
+    h0 = synth.noise_film(37, 23, seed=5)
+    h = gpu(h0)
+    g.bind(h)
+    dt, log = g.advance(0, 0.1, log=True)
+    assert dt == 0.1 and log == [] and torch.equal(h, gpu(h0))
+    dt, _ = g.advance(2, 0.1)
+    snap = h.clone()
+    dt2, _ = g.advance(0, dt)
+    assert dt2 == dt and torch.equal(h, snap)
+    with pytest.raises(TFError):
+        g.advance(-1, dt)
