@@ -308,3 +308,31 @@ def test_zero_and_negative_step_counts():
     assert dt2 == dt and torch.equal(h, snap)
     with pytest.raises(TFError):
         g.advance(-1, dt)
+
+
+@pytest.mark.parametrize("n,m", [(5, 2), (4, 3), (9, 3), (3, 1)])
+@pytest.mark.parametrize("nx,ny", [(37, 23), (130, 67)])
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_general_power_law_matches_oracle(orc, n, m, nx, ny, theta):
+    """Exponents other than n = 3, m = 2 take the general power-law instantiation of the
+    sweeps (powers of r = 1/h by repeated multiplication): D(u) to 1e-12 and three Newton
+    iterates to 1e-10 of the update, as for the n = 3, m = 2 path."""
+    ds, dt = 0.67347, 0.2
+    M = omodel(orc, n=float(n), m=float(m))
+    g = Grid(nx, ny, ds)
+    g.set_model(10.0, 0.1, n, m)
+    g.set_scheme(theta=theta)
+    un = synth.noise_film(nx, ny, seed=n * 100 + m + nx, amp=0.05)
+    out = torch.empty((ny, nx), dtype=torch.float64, device=DEV)
+    g.flux_divergence(gpu(un), out)
+    ref = orc.flux_divergence(M, un, ds)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+    uk, uk_g, un_g = un, gpu(un), gpu(un)
+    for it in range(3):
+        e, r, flags = g.newton_iteration(un_g, uk_g, out, dt)
+        ref, e_ref, _ = orc.adi_iteration(M, un, uk, ds, dt, theta)
+        got = out.cpu().numpy()
+        assert flags == 0
+        assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref - uk)) + 1e-15, it
+        assert e == pytest.approx(e_ref, rel=1e-8)
+        uk, uk_g = got, out.clone()
