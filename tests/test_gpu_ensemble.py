@@ -215,3 +215,25 @@ def test_full_ensemble_matches_oracle_on_sampled_films(orc):
         got = ens.view(packed, int(f)).cpu().numpy()
         assert np.max(np.abs(got - u) / u) <= 1e-10, f
         assert dts[f] == dt, f
+
+
+def test_general_power_law_ensemble_equals_single_film_path_bitwise():
+    """Exponents n = 5, m = 2 (the general power-law instantiation of the ensemble passes):
+    every film equals its single-film run bit for bit."""
+    nx, ny, kap, ds, h0 = films_setup(FILMS)
+    ens = Ensemble(nx, ny, ds, kap, b=0.1, n=5, m=2)
+    ens.set_scheme(tol=1e-10)
+    packed = pack(ens, h0)
+    ens.bind(packed)
+    st, _, sts, its = ens.step(3, 0.1)
+    assert st == TF_OK and all(s == TF_OK for s in sts)
+    for f in range(len(FILMS)):
+        g = Grid(nx[f], ny[f], ds[f])
+        g.set_model(kap[f], 0.1, 5, 2)
+        g.set_scheme(tol=1e-10)
+        h = torch.from_numpy(h0[f]).to(DEV)
+        g.bind(h)
+        s1, _, log = g.try_advance(3, 0.1)
+        assert s1 == TF_OK
+        assert torch.equal(ens.view(packed, f), h), f
+        assert its[f] == sum(x["total_iters"] for x in log)
