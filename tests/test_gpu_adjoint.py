@@ -282,3 +282,26 @@ def test_rollout_other_models_and_theta_match_finite_differences(model, theta):
             Lp = _loss(rollout(p0, kap + ek, base, steps, dt, ds, **kw), target).item()
             Lm = _loss(rollout(p0, kap - ek, base, steps, dt, ds, **kw), target).item()
             assert kap.grad.item() == pytest.approx((Lp - Lm) / (2 * ek), rel=1e-6)
+
+
+def test_adjoint_step_general_power_law_matches_oracle(orc):
+    """Exponents n = 5, m = 2 (the general power-law adjoint kernels): one adjoint step and
+    its dL/dkappa contribution against the oracle, and J_D^T against the oracle's transpose."""
+    nx, ny, ds, dt = 40, 30, 0.67347, 0.1
+    M = orc.Model(kappa=10.0, b=0.1, n=5.0, m=2.0)
+    un = synth.noise_film(nx, ny, seed=8, amp=0.01)
+    unp1, res = orc.step(M, orc.Scheme(theta=1.0, tol=1e-14), un, ds, dt)
+    assert res.status == orc.OK
+    lam = np.random.default_rng(9).standard_normal((ny, nx))
+    ref, gk_ref, _ = orc.adjoint_step(M, un, unp1, lam, ds, dt, 1.0, tol=1e-14)
+    g = Grid(nx, ny, ds)
+    g.set_model(10.0, 0.1, 5, 2)
+    g.set_scheme(theta=1.0)
+    out = torch.empty((ny, nx), dtype=torch.float64, device=DEV)
+    g.jacobian_apply_t(gpu(unp1), gpu(lam), out)
+    jt_ref = orc.jacobian_apply_t(M, unp1, lam, ds)
+    assert np.max(np.abs(out.cpu().numpy() - jt_ref)) <= 1e-12 * np.max(np.abs(jt_ref))
+    lg = gpu(lam)
+    gk, _ = g.adjoint_step(gpu(un), gpu(unp1), dt, lg, tol=1e-14)
+    assert np.max(np.abs(lg.cpu().numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
+    assert gk == pytest.approx(gk_ref, rel=1e-9)
