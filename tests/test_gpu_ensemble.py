@@ -237,3 +237,35 @@ def test_general_power_law_ensemble_equals_single_film_path_bitwise():
         assert s1 == TF_OK
         assert torch.equal(ens.view(packed, f), h), f
         assert its[f] == sum(x["total_iters"] for x in log)
+
+
+def test_film_info_matches_single_film_log():
+    """tf_ensemble_film_info after a call: time, last dt, Newton iterations and update ratio
+    of each film's last step equal the single-film path's log of the same steps."""
+    nx, ny, kap, ds, h0 = films_setup(FILMS[:4])
+    kw = dict(tol=1e-10, max_newton=10, adaptive=1, dt_min=1e-6, dt_max=1.0, dt_shrink=0.5, dt_grow=1.1,
+              grow_after=2)
+    ens = Ensemble(nx, ny, ds, kap)
+    ens.set_scheme(**kw)
+    packed = pack(ens, h0)
+    ens.bind(packed)
+    st, _, _, _ = ens.step(5, 0.5)
+    assert st == TF_OK
+    for f in range(4):
+        s1, _, log, _ = single(nx[f], ny[f], ds[f], kap[f], h0[f], 5, 0.5, **kw)
+        assert s1 == TF_OK
+        info = ens.film_info(f)
+        last = log[-1]
+        assert info["t"] == last["t"] and info["dt_used"] == last["dt_used"], f
+        assert info["newton_iters"] == last["newton_iters"] and info["e_final"] == last["e_final"], f
+        assert info["status"] == TF_OK
+
+
+def test_scheme_round_trip():
+    g = Grid(16, 12, 0.5)
+    kw = dict(theta=0.5, tol=3e-11, max_newton=17, adaptive=1, dt_min=1e-7, dt_max=2.5, dt_shrink=0.25,
+              dt_grow=1.3, grow_after=4)
+    g.set_scheme(**kw)
+    s = g.scheme()
+    for k, v in kw.items():
+        assert getattr(s, k) == v, k
