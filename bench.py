@@ -180,7 +180,9 @@ def bench_ensemble(args):
            "newton_iters_total": int(sum(its)), "loop_newton_iters_total": loop_iters,
            "bitwise_equal_to_loop": bool(same), "status_ok": st == 0,
            "dt_range": [min(dts), max(dts)],
-           "cell_iterations_per_s": sum(n * n * i for n, i in zip(nx, its)) / t_ens}
+           "cell_iterations_per_s": sum(n * n * i for n, i in zip(nx, its)) / t_ens,
+           # 48 algorithmic bytes per cell per Newton iteration of each film still iterating
+           "iteration_roofline_frac": 48.0 * sum(n * n * i for n, i in zip(nx, its)) / t_ens / (HBM_PEAK_GBS * 1e9)}
     print(json.dumps(out), flush=True)
 
 
