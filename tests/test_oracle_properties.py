@@ -20,7 +20,7 @@ def make(orc, kind):
     return orc.Model.polymer(), 3.9
 
 
-@settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@settings(max_examples=300, derandomize=True, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
 @given(kind=MODELS, nx=st.integers(3, 11), ny=st.integers(3, 11), theta=st.sampled_from([0.5, 1.0]),
        dtf=st.floats(0.01, 1.0), dsf=st.floats(0.5, 2.0), seed=st.integers(0, 2 ** 31 - 1))
 def test_step_invariants(orc, kind, nx, ny, theta, dtf, dsf, seed):
