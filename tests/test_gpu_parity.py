@@ -336,3 +336,29 @@ def test_general_power_law_matches_oracle(orc, n, m, nx, ny, theta):
         assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref - uk)) + 1e-15, it
         assert e == pytest.approx(e_ref, rel=1e-8)
         uk, uk_g = got, out.clone()
+
+
+def _random_cases(n=30, seed=2024):
+    rng = np.random.default_rng(seed)
+    return [(int(rng.integers(4, 300)), int(rng.integers(4, 300)), float(rng.choice([0.5, 1.0])),
+             float(rng.uniform(0.02, 1.0))) for _ in range(n)]
+
+
+@pytest.mark.parametrize("nx,ny,theta,dt", _random_cases())
+def test_random_shapes_newton_iteration(orc, nx, ny, theta, dt):
+    """Seeded draws of film shapes (4..299 cells a side), theta and dt: two Newton iterates
+    against the oracle to 1e-10 of the update, and the reduction record."""
+    ds = 0.67347
+    un = synth.noise_film(nx, ny, seed=nx * 331 + ny, amp=0.02)
+    g = make_grid(nx, ny, ds, theta=theta)
+    M = omodel(orc)
+    uk, uk_g, un_g = un, gpu(un), gpu(un)
+    out = torch.empty_like(un_g)
+    for it in range(2):
+        e, r, flags = g.newton_iteration(un_g, uk_g, out, dt)
+        ref, e_ref, _ = orc.adi_iteration(M, un, uk, ds, dt, theta)
+        got = out.cpu().numpy()
+        assert flags == 0
+        assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref - uk)) + 1e-15, (it, nx, ny)
+        assert e == pytest.approx(e_ref, rel=1e-8)
+        uk, uk_g = got, out.clone()
