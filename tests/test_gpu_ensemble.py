@@ -269,3 +269,25 @@ def test_scheme_round_trip():
     s = g.scheme()
     for k, v in kw.items():
         assert getattr(s, k) == v, k
+
+
+def test_random_ragged_ensemble_equals_single_films_bitwise():
+    """Twelve seeded random films (4..299 cells a side, kappa in [5, 20]) in one ensemble,
+    adaptive dt: each film equals its single-film run bit for bit, with the same iterations."""
+    rng = np.random.default_rng(77)
+    films = [(int(rng.integers(4, 300)), int(rng.integers(4, 300)), float(rng.uniform(5.0, 20.0)))
+             for _ in range(12)]
+    nx, ny, kap, ds, h0 = films_setup(films)
+    kw = dict(tol=1e-10, max_newton=10, adaptive=1, dt_min=1e-9, dt_max=1.0, dt_shrink=0.5, dt_grow=1.1,
+              grow_after=2)
+    ens = Ensemble(nx, ny, ds, kap)
+    ens.set_scheme(**kw)
+    packed = pack(ens, h0)
+    ens.bind(packed)
+    st, dts, sts, its = ens.step(4, 0.2)
+    assert st == TF_OK and all(s == TF_OK for s in sts)
+    for f in range(len(films)):
+        s1, dtn, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 4, 0.2, **kw)
+        assert s1 == TF_OK
+        assert torch.equal(ens.view(packed, f), h), films[f]
+        assert its[f] == sum(x["total_iters"] for x in log) and dts[f] == dtn, films[f]
