@@ -1,7 +1,8 @@
 """Throughput benchmark of the FP64 ADI-Newton thin-film step on one MI355X.
 
 Workload (default): the 8192^2 film, L = 256 lambda_m, h0 = 1 + 0.01 U[-1,1] (seed 2),
-backward Euler dt = 0.2, Newton tol 1e-10, fixed dt. A "step" is one accepted time
+backward Euler dt = 0.2, Newton tol 1e-10, fixed dt, 500 steps (the default K; each
+workload has its own default step count). A "step" is one accepted time
 step (every Newton iteration of it: residual, y sweep, x sweep, update, reductions).
 W untimed warm-up steps are taken first, then exactly K steps are timed between
 stream synchronisations with the state resident in HBM.
@@ -295,7 +296,9 @@ def bench_spectrum(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps; default: the workload's own count (single film: the config's steps, "
+                         "500 for the 8192^2 film; ensemble: 10; adjoint: 400; spectrum: 60)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="large8192")
     ap.add_argument("--workload", default="single", choices=["single", "ensemble", "adjoint", "spectrum"],
@@ -328,6 +331,14 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps is None:
+        args.steps = {"ensemble": 10, "adjoint": 400, "spectrum": 60}.get(args.workload)
+    if args.steps is None:
+        from paper_1806_10550_amd import synth
+        args.steps = synth.CONFIGS[args.config].steps
+    if args.steps < 1:
+        print("--steps must be >= 1", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "ensemble":
