@@ -298,7 +298,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps; default: the workload's own count (single film: the config's steps, "
-                         "500 for the 8192^2 film; ensemble: 10; adjoint: 400; spectrum: 60)")
+                         "500 for the 8192^2 film; ensemble: 300; adjoint: 400; spectrum: 60)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="large8192")
     ap.add_argument("--workload", default="single", choices=["single", "ensemble", "adjoint", "spectrum"],
@@ -333,7 +333,7 @@ def main():
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if args.steps is None:
-        args.steps = {"ensemble": 10, "adjoint": 400, "spectrum": 60}.get(args.workload)
+        args.steps = {"ensemble": 300, "adjoint": 400, "spectrum": 60}.get(args.workload)
     if args.steps is None:
         from paper_1806_10550_amd import synth
         args.steps = synth.CONFIGS[args.config].steps
