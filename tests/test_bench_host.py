@@ -51,3 +51,9 @@ def test_counter_summaries_are_usable():
         assert rec["fetch_kib"] + rec["write_kib"] >= algo_kib, k
     flops = bench.fp64_flops_for("solve_x")
     assert flops is not None and flops > 100 * 8192 * 8192
+
+
+def test_step_count_must_be_positive():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "0"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "--steps" in r.stderr
