@@ -92,6 +92,7 @@ struct ChainParams {
 };
 
 enum ResultWord { RES_EMAX = 0, RES_RMAX = 1, RES_FLAGS = 2, RES_WORDS = 8 };
+constexpr int ENS_RES_SPREAD = 16;    // copies of each film's reduction record in the ensemble
 // A grid's reduction record is spread over RES_SPREAD copies (workgroup b updates copy
 // b % RES_SPREAD) so that the atomics of thousands of workgroups do not all meet at
 // one address; the host combines the copies.
@@ -110,7 +111,9 @@ struct FilmState {         // per-film Newton / time-step state, updated on the 
     double dt, t, dt_used, e_last, r_last;
     int k, cur, it, nxt;   // iteration in the attempt; buffer index of u^n, u_k, u_{k+1} (0,1,2)
     int active, status, successes, rejections, newton, total;
-    unsigned long long red[4]; // reduction words of the current iteration (RES_EMAX..)
+    // reduction words of the current iteration: ENS_RES_SPREAD copies of RES_WORDS words
+    // (RES_EMAX..), so that the waves of a large film do not all update one address
+    unsigned long long red[ENS_RES_SPREAD * RES_WORDS];
 };
 
 struct EnsScheme {

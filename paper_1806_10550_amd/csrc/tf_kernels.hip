@@ -548,7 +548,7 @@ __global__ void TF_PASS_ATTR k_pass_ens(EnsParams e)
     p.rel = e.rel + d.roff * NREL;
     p.ext = e.ext + d.roff * NEXT;
     p.res = s->red;
-    p.res_spread = 1;
+    p.res_spread = ENS_RES_SPREAD;
     tile_body<DIR, SOLVE, KM>(p, tx, ty);
 }
 
@@ -937,12 +937,19 @@ __global__ void __launch_bounds__(256) k_ens_control(FilmState *st, int nfilms, 
     for (int f = threadIdx.x; f < nfilms; f += 256) {
         FilmState &s = st[f];
         if (!s.active) continue;
-        const double e = __longlong_as_double((long long)s.red[RES_EMAX]);
-        const double r = __longlong_as_double((long long)s.red[RES_RMAX]);
-        const unsigned long long flags = s.red[RES_FLAGS];
-        s.red[RES_EMAX] = 0ull;
-        s.red[RES_RMAX] = 0ull;
-        s.red[RES_FLAGS] = 0ull;
+        // combine the copies (maxima of non-negative doubles compare as bit patterns), clear them
+        unsigned long long em = 0ull, rm = 0ull, flags = 0ull;
+        for (int c = 0; c < ENS_RES_SPREAD; ++c) {
+            unsigned long long *w = s.red + c * RES_WORDS;
+            em = w[RES_EMAX] > em ? w[RES_EMAX] : em;
+            rm = w[RES_RMAX] > rm ? w[RES_RMAX] : rm;
+            flags |= w[RES_FLAGS];
+            w[RES_EMAX] = 0ull;
+            w[RES_RMAX] = 0ull;
+            w[RES_FLAGS] = 0ull;
+        }
+        const double e = __longlong_as_double((long long)em);
+        const double r = __longlong_as_double((long long)rm);
         s.k += 1;
         s.total += 1;
         s.e_last = e;
@@ -1009,9 +1016,11 @@ __global__ void __launch_bounds__(256) k_ens_begin(FilmState *st, int nfilms)
     s.it = s.cur;
     s.nxt = s.cur == 0 ? 1 : 0;
     s.rejections = 0;
-    s.red[RES_EMAX] = 0ull;
-    s.red[RES_RMAX] = 0ull;
-    s.red[RES_FLAGS] = 0ull;
+    for (int c = 0; c < ENS_RES_SPREAD; ++c) {
+        s.red[c * RES_WORDS + RES_EMAX] = 0ull;
+        s.red[c * RES_WORDS + RES_RMAX] = 0ull;
+        s.red[c * RES_WORDS + RES_FLAGS] = 0ull;
+    }
 }
 
 // Copy every film's accepted state back into buffer 0 (the caller's).
