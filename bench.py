@@ -5,11 +5,13 @@ backward Euler dt = 0.2, Newton tol 1e-10, fixed dt, 500 steps (the default K; e
 workload has its own default step count). A "step" is one accepted time
 step (every Newton iteration of it: residual, y sweep, x sweep, update, reductions).
 W untimed warm-up steps are taken first, then exactly K steps are timed between
-stream synchronisations with the state resident in HBM.
+stream synchronisations with the state resident in HBM; the same window is run three
+times from the same state (bit-identical work) and the median is reported.
 
-Printed: one JSON line with steps/s, the roofline record of the dominant kernel
-(algorithmic bytes per launch over its mean HIP-event duration) and the oracle's
-rate on the host (a bounded sample, see cpu_baseline.sample).
+Printed: one JSON line with steps/s, the roofline record of one Newton iteration's
+kernels (48 algorithmic bytes per cell over their mean time per iteration, from HIP
+events around every launch in a fourth, profiled run of the window) and the oracle's
+rate on the host (one full step of the same film, see cpu_baseline.sample).
 """
 import argparse
 import hashlib
@@ -26,9 +28,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("ADI steps/s & HBM GB/s (FP64, 2048²/8192²); ensemble + adjoint cost vs forward")
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per cell for each kernel class (one read of each input field and
-# one write of the output field of its sweep; the y sweep reads u_k and b^n and writes w,
-# the x sweep reads u_k and w and writes u_{k+1}: 48 B per cell per Newton iteration).
+# Algorithmic bytes per cell per Newton iteration: the y sweep must read u_k and b^n and
+# write w, the x sweep read u_k and w and write u_{k+1}, each once: 48 B.
+ALGO_BYTES_PER_CELL_ITERATION = 48.0
+# The bytes of each kernel class taken alone (the inputs it reads, the field it writes).
 ALGO_BYTES_PER_CELL = {"relations_y": 16, "solve_y": 24, "relations_x": 16, "solve_x": 24}
 KERNEL_SOURCES = ["paper_1806_10550_amd/csrc/tf_kernels.hip", "paper_1806_10550_amd/csrc/tf_internal.h",
                   "paper_1806_10550_amd/csrc/tf_device.h"]
@@ -70,6 +73,24 @@ def copy_rate_gbs():
         return None
 
 
+def iteration_traffic(ncells):
+    """HBM bytes of one Newton iteration (the six sweep launches) from the committed counter
+    summary, or None when absent or taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    ks = t.get("kernels", {})
+    per = {"relations_y": 1, "solve_y": 1, "relations_x": 1, "solve_x": 1, "chain": 2}
+    if any(k not in ks for k in per):
+        return None
+    return sum(n * (ks[k]["fetch_kib"] + ks[k]["write_kib"]) * 1024.0 * t.get("copy_scale", 1.0)
+               for k, n in per.items())
+
+
 def traffic_for(kernel, ncells):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None when
     absent or taken on different kernel sources."""
@@ -84,32 +105,38 @@ def traffic_for(kernel, ncells):
     return (k["fetch_kib"] + k["write_kib"]) * 1024.0 * t.get("copy_scale", 1.0)
 
 
-def cpu_baseline(h_np, ds, dt, iters_per_step, model="power"):
-    """Oracle (plain C, OpenMP over lines) timed for ONE Newton iteration of the same
-    film; steps/s = 1 / (t_iteration * mean Newton iterations per step of the GPU run)."""
+def cpu_baseline(h_np, ds, dt, scheme, successes, model="power"):
+    """The oracle (plain C, OpenMP over independent lines) timed on the host cores for ONE
+    full accepted step (every Newton iteration of it) of the same film from the state the
+    GPU run ended at, with the same scheme: steps/s = 1 / t_step. Also per Newton iteration
+    (the unit that does not depend on the step window) and one thread on a 1/64 sub-film."""
     from oracle import oracle as orc
     threads = len(os.sched_getaffinity(0))
     orc.set_threads(threads)
     M = orc.Model(kappa=10.0, b=0.1, n=3.0, m=2.0) if model == "power" else getattr(orc.Model, model)()
+    S = orc.Scheme(**scheme)
     t0 = time.perf_counter()
-    orc.adi_iteration(M, h_np, h_np, ds, dt, 1.0)
-    t_it = time.perf_counter() - t0
+    _, res = orc.step(M, S, h_np, ds, dt, successes)
+    t_step = time.perf_counter() - t0
+    iters = res.total_iters
     cores = orc.get_threads()
-    # one thread, on the top-left quarter by quarter of the film (1/16 of the cells), scaled
+    # one thread: one Newton iteration on the top-left eighth by eighth of the film, scaled
     # by the cell count
-    sub = np.ascontiguousarray(h_np[: h_np.shape[0] // 4, : h_np.shape[1] // 4])
+    sub = np.ascontiguousarray(h_np[: max(h_np.shape[0] // 8, 4), : max(h_np.shape[1] // 8, 4)])
     orc.set_threads(1)
     t0 = time.perf_counter()
-    orc.adi_iteration(M, sub, sub, ds, dt, 1.0)
+    orc.adi_iteration(M, sub, sub, ds, dt, scheme.get("theta", 1.0))
     t_1 = (time.perf_counter() - t0) * (h_np.size / sub.size)
     orc.set_threads(threads)
-    return {"value": 1.0 / (t_it * iters_per_step), "unit": "steps/s", "cores": cores,
-            "kind": "oracle",
-            "sample": (f"one Newton iteration on the full {h_np.shape[1]}x{h_np.shape[0]} film "
-                       f"({t_it:.2f} s), scaled by the GPU run's {iters_per_step:.2f} iterations/step"),
-            "single_thread_value": 1.0 / (t_1 * iters_per_step),
+    return {"value": 1.0 / t_step, "unit": "steps/s", "cores": cores, "kind": "oracle",
+            "sample": (f"one accepted step of the {h_np.shape[1]}x{h_np.shape[0]} film from the state the GPU "
+                       f"run ended at ({iters} Newton iterations, {t_step:.2f} s, status {res.status})"),
+            "newton_iters": iters,
+            "ms_per_newton_iteration": 1e3 * t_step / max(iters, 1),
+            "grid_point_iterations_per_s": h_np.size * iters / t_step,
+            "single_thread_ms_per_newton_iteration": 1e3 * t_1,
             "single_thread_sample": (f"one Newton iteration on {sub.shape[1]}x{sub.shape[0]} cells of the same "
-                                     f"film on one thread, scaled to the full film ({t_1:.1f} s per iteration)")}
+                                     f"film on one thread, scaled to the full film")}
 
 
 def bench_ensemble(args):
@@ -377,35 +404,57 @@ def main():
                     f"noise 0.01 H0 seed {cfg.seed}, backward Euler dt={dt0:.4g} (dt omega_m as {cfg.name}), "
                     f"tol {cfg.tol}, fixed dt")
     h = torch.from_numpy(h_np).to(dev)
-    g.set_scheme(theta=1.0, tol=cfg.tol, max_newton=5000, adaptive=cfg.adaptive)
+    if cfg.adaptive:
+        scheme = dict(theta=1.0, tol=cfg.tol, max_newton=10, adaptive=1, dt_min=1e-6, dt_max=1.0, dt_shrink=0.5,
+                      dt_grow=1.1, grow_after=5)
+        workload = workload.replace("fixed dt", "adaptive dt (K=10)")
+    else:
+        scheme = dict(theta=1.0, tol=cfg.tol, max_newton=5000, adaptive=0)
+    g.set_scheme(**scheme)
     g.bind(h)
     dt = dt0
     if args.warmup > 0:
         dt, _ = g.advance(args.warmup, dt)
+    # the timed window starts from this state; every run below repeats it exactly
     torch.cuda.synchronize()
-    g.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    dt, log = g.advance(args.steps, dt, log=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = g.profile_read()
-    g.profile(False)
+    saved, (t_clock, succ), dt_start = h.clone(), g.clock(), dt
+
+    def run(profiled):
+        h.copy_(saved)
+        g.set_clock(t_clock, succ)
+        g.profile(profiled)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dt_end, log = g.advance(args.steps, dt_start, log=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = g.profile_read() if profiled else None
+        g.profile(False)
+        return el, log, prof, dt_end
+
+    # headline: median of three unprofiled runs of the same window (no events in them)
+    runs = sorted((run(False) for _ in range(3)), key=lambda r: r[0])
+    elapsed, log, _, dt_end = runs[1]
+    # kernel breakdown: one more run of the same window with an event pair per launch
+    el_prof, log_prof, prof, _ = run(True)
     iters = [x["newton_iters"] for x in log]
     total_iters = sum(x["total_iters"] for x in log)
+    assert sum(x["total_iters"] for x in log_prof) == total_iters
     ncells = n * n
     steps_per_s = args.steps / elapsed
 
-    # dominant kernel by total event time
-    dom = max(ALGO_BYTES_PER_CELL, key=lambda k: prof[k][0])
-    ms, cnt = prof[dom]
-    avg_s = ms / 1e3 / max(cnt, 1)
-    algo_bytes = ALGO_BYTES_PER_CELL[dom] * ncells
-    achieved = algo_bytes / avg_s / 1e9
-    # the counter summary covers the n = 3, m = 2 kernels only
-    traffic = traffic_for(dom, ncells) if args.model == "power" else None
+    # The roofline record covers the kernels of one Newton iteration (the six launches of the
+    # y and x sweeps) as a unit: 48 algorithmic bytes per cell per iteration (each sweep reads
+    # its two inputs and writes its output once) over their mean time per iteration from the
+    # per-launch HIP events of the profiled run.
+    sweep = ["relations_y", "chain_y", "solve_y", "relations_x", "chain_x", "solve_x"]
+    iter_kernel_s = sum(prof[k][0] for k in sweep) / 1e3 / total_iters
+    achieved = ALGO_BYTES_PER_CELL_ITERATION * ncells / iter_kernel_s / 1e9
+    traffic = iteration_traffic(ncells) if args.model == "power" else None
     kernel_ms = sum(v[0] for v in prof.values())
-    iter_frac = (48.0 * ncells * total_iters) / (elapsed * HBM_PEAK_GBS * 1e9)
+    iter_frac = (ALGO_BYTES_PER_CELL_ITERATION * ncells * total_iters) / (elapsed * HBM_PEAK_GBS * 1e9)
+    dom = max(ALGO_BYTES_PER_CELL, key=lambda k: prof[k][0])
+    dom_s = prof[dom][0] / 1e3 / max(prof[dom][1], 1)
 
     out = {
         "metric": METRIC,
@@ -421,28 +470,35 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": workload, "nx": n, "ny": n, "dt": dt0, "tol": cfg.tol},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": "newton_iteration (" + ", ".join(sweep) + ")",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
+        "ms_per_newton_iteration": 1e3 * elapsed / total_iters,
+        "kernel_ms_per_newton_iteration": 1e3 * iter_kernel_s,
         "newton_iters_per_step": total_iters / args.steps,
         "newton_iters_distribution": {"min": min(iters), "median": sorted(iters)[len(iters) // 2],
                                       "max": max(iters)},
+        "runs_s": [r[0] for r in runs],
+        "profiled_run_s": el_prof,
         "copy_kernel_gbs": copy_rate_gbs(),
-        # FP64 arithmetic rate of the same kernel (flops per launch from the committed SQ
-        # counters over the live mean duration) against the 78.6 TFLOP/s FP64 vector peak
-        "fp64_alu": ({"achieved": fp64_flops_for(dom) / avg_s / 1e12, "peak": 78.6, "unit": "TFLOP/s",
-                      "frac": fp64_flops_for(dom) / avg_s / 78.6e12} if fp64_flops_for(dom) else None),
-        "achieved_frac_of_copy": (achieved / copy_rate_gbs()) if copy_rate_gbs() else None,
         "grid_point_steps_per_s": steps_per_s * ncells,
         "grid_point_iterations_per_s": total_iters * ncells / elapsed,
+        # the same 48 B per cell-iteration over the whole wall time of the timed window
         "iteration_roofline_frac": iter_frac,
         "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
         "kernel_launches": {k: v[1] for k, v in prof.items()},
-        "kernel_busy_frac": kernel_ms / (1e3 * elapsed),
+        "kernel_mean_us": {k: round(1e3 * v[0] / v[1], 2) for k, v in prof.items() if v[1]},
+        "kernel_busy_frac": kernel_ms / (1e3 * el_prof),
+        # the longest kernel class alone, with its own share of the bytes (counters: actual HBM
+        # bytes per launch) and its FP64 rate from the committed SQ counters
+        "dominant_kernel": {"kernel": dom, "mean_us": 1e6 * dom_s,
+                            "algorithmic_gbs": ALGO_BYTES_PER_CELL[dom] * ncells / dom_s / 1e9,
+                            "traffic": traffic_for(dom, ncells) if args.model == "power" else None,
+                            "fp64_tflops": (fp64_flops_for(dom) / dom_s / 1e12) if fp64_flops_for(dom) else None},
     }
     if not args.no_cpu_baseline:
         h_now = h.cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(h_now, ds, dt, total_iters / args.steps, args.model)
+        out["cpu_baseline"] = cpu_baseline(h_now, ds, dt_end, scheme, g.clock()[1], args.model)
     print(json.dumps(out), flush=True)
     g.close()
 

@@ -1,16 +1,22 @@
-"""Compile libthinfilm.so (HIP, gfx950) in-tree with hipcc."""
+"""Compile libthinfilm.so (HIP, gfx950) in-tree with hipcc.
+
+Each source is compiled to an object file in its own hipcc process (in parallel), then
+the objects are linked into the shared library.
+"""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libthinfilm.so")
+OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["tf_kernels.hip", "tf_api.hip", "tf_ensemble.hip", "tf_adjoint.hip", "tf_spectrum.hip"]
 LIBS = ["-lhipfft"]
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-result",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -18,8 +24,20 @@ FLAGS = [
 
 
 def build(verbose: bool = False, extra=None) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = ["hipcc"] + FLAGS + (extra or []) + srcs + LIBS + ["-o", LIB + ".tmp"]
+    os.makedirs(OBJDIR, exist_ok=True)
+    extra = list(extra or [])
+
+    def compile_one(src):
+        obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+        cmd = ["hipcc"] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC"] + extra + objs + LIBS + ["-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -28,5 +46,4 @@ def build(verbose: bool = False, extra=None) -> str:
 
 
 if __name__ == "__main__":
-    extra = sys.argv[1:]
-    print(build(verbose=True, extra=extra))
+    print(build(verbose=True, extra=sys.argv[1:]))

@@ -125,6 +125,8 @@ struct tf_grid {
     double *buf[2] = {nullptr, nullptr};
     double *w = nullptr, *bn = nullptr, *rel = nullptr, *ext = nullptr, *chain = nullptr;
     double *partials = nullptr, *hpart = nullptr;
+    double *mpart = nullptr;   // per x-solve tile mass records {s, c, min, -} of the last iterate
+    double *mout = nullptr;    // {sum, min} combined from mpart
     unsigned long long *res = nullptr, *hres = nullptr;
     int Px = 0, Py = 0;
     long iter = 0;
@@ -191,7 +193,8 @@ tf::PassParams base_params(const tf_grid *g, double dt)
 // One ADI-Newton iteration: y sweep (relations, chain, solve) into w, x sweep into
 // u_kp1. The reduction record of slot `slot` receives max|G| (y relations pass) and
 // max|v/u_k| and flags (x solve pass); slot (slot+2)%RES_SLOTS is cleared for later.
-tf_status enqueue_iteration(tf_grid *g, const double *bnp, const double *uk, double *ukp1, double dt, int slot)
+tf_status enqueue_iteration(tf_grid *g, const double *bnp, const double *uk, double *ukp1, double dt, int slot,
+                            bool diag = false)
 {
     tf::PassParams P = base_params(g, dt);
     P.u = uk;
@@ -222,6 +225,7 @@ tf_status enqueue_iteration(tf_grid *g, const double *bnp, const double *uk, dou
     tf::ChainParams Cx{g->ny, g->Px, g->rel, g->chain, g->ext};
     if ((st = timed(g, P_CHAIN_X, [&] { return tf::launch_chain(Cx, g->stream); })) != TF_OK) return st;
     P.res = res;
+    P.mass = diag ? g->mpart : nullptr; // mass diagnostic of u_{k+1}, formed as it is stored
     if ((st = timed(g, P_SOLVE_X, [&] { return tf::launch_pass(1, true, P, g->stream); })) != TF_OK) return st;
     return TF_OK;
 }
@@ -280,6 +284,22 @@ tf_status mass_of(tf_grid *g, const double *u, double *mass, double *hmin, bool 
     *mass = s + c;
     *hmin = m;
     if (nan) *nan = isn;
+    return TF_OK;
+}
+
+int x_tiles(const tf_grid *g) { return g->Px * ((g->ny + tf::TILE - 1) / tf::TILE); }
+
+// Mass and minimum of the last iterate from the records its x solve left per tile (Sec.
+// "Conservation of Mass"), combined on the device in a fixed order: no extra read of h.
+tf_status fused_mass(tf_grid *g, double *mass, double *hmin)
+{
+    tf_status st = timed(g, P_MASS, [&] { return tf::launch_mass_tiles(g->mpart, x_tiles(g), g->mout, g->stream); });
+    if (st != TF_OK) return st;
+    TF_HIP(hipMemcpyAsync(g->hpart, g->mout, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    TF_HIP(hipStreamSynchronize(g->stream));
+    if (g->prof) prof_flush(g);
+    *mass = g->hpart[0];
+    *hmin = g->hpart[1];
     return TF_OK;
 }
 
@@ -344,7 +364,8 @@ tf_status do_step(tf_grid *g, double *dt_inout, tf_step_info *info)
         for (iters = 1; iters <= g->S.max_newton; ++iters) {
             double *dst = pick_buffer(g, un, uk);
             const int slot = (int)(g->iter % RES_SLOTS);
-            if ((st = enqueue_iteration(g, bnp, uk, dst, dt, slot)) != TF_OK) return st;
+            if ((st = enqueue_iteration(g, bnp, uk, dst, dt, slot, info != nullptr && g->diag_mass)) != TF_OK)
+                return st;
             g->iter++;
             int flags = 0;
             if ((st = read_result(g, slot, &e, &r, &flags)) != TF_OK) return st;
@@ -387,8 +408,9 @@ tf_status do_step(tf_grid *g, double *dt_inout, tf_step_info *info)
     }
     *dt_inout = dt;
     if (info && g->diag_mass) {
+        // the accepted state is the last iterate: its x solve left the mass records
         double m, hm;
-        if ((st = mass_of(g, g->cur, &m, &hm, nullptr)) != TF_OK) return st;
+        if ((st = fused_mass(g, &m, &hm)) != TF_OK) return st;
         info->mass = m;
         info->hmin = hm;
     }
@@ -451,6 +473,8 @@ tf_status tf_create(int nx, int ny, double ds, void *stream, tf_grid **out)
               && hipMalloc(&g->ext, lines_seg * tf::NEXT * sizeof(double)) == hipSuccess
               && hipMalloc(&g->chain, lines_seg * tf::NCHAIN * sizeof(double)) == hipSuccess
               && hipMalloc(&g->partials, 4096 * 4 * sizeof(double)) == hipSuccess
+              && hipMalloc(&g->mpart, (size_t)x_tiles(g) * 4 * sizeof(double)) == hipSuccess
+              && hipMalloc(&g->mout, 2 * sizeof(double)) == hipSuccess
               && hipMalloc(&g->res, RES_SLOTS * RES_STRIDE * sizeof(unsigned long long)) == hipSuccess
               && hipHostMalloc(&g->hres, RES_STRIDE * sizeof(unsigned long long), hipHostMallocDefault) == hipSuccess
               && hipHostMalloc(&g->hpart, 4096 * 4 * sizeof(double), hipHostMallocDefault) == hipSuccess;
@@ -482,6 +506,8 @@ tf_status tf_destroy(tf_grid *g)
     (void)hipFree(g->ext);
     (void)hipFree(g->chain);
     (void)hipFree(g->partials);
+    (void)hipFree(g->mpart);
+    (void)hipFree(g->mout);
     (void)hipFree(g->res);
     if (g->hres) (void)hipHostFree(g->hres);
     if (g->hpart) (void)hipHostFree(g->hpart);

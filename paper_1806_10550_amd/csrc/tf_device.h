@@ -370,6 +370,24 @@ __device__ __forceinline__ void chain_numeric(const double *sB, int lane, int Q,
     }
 }
 
+// Neumaier's compensated accumulation: s + c carries the running sum, c the rounding errors
+// of the additions (each recovered exactly by the two-sum identity).
+__device__ __forceinline__ void two_sum_acc(double &s, double &c, double x)
+{
+    const double t = s + x;
+    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+}
+
+// Combine two compensated partial sums (s, c) += (s2, c2); symmetric in its operands, so a
+// butterfly over the lanes of a wave leaves the same value in every lane.
+__device__ __forceinline__ void comp_add(double &s, double &c, double s2, double c2)
+{
+    double cc = c + c2;
+    two_sum_acc(s, cc, s2);
+    c = cc;
+}
+
 __device__ __forceinline__ double wave_max(double v)
 {
 #pragma unroll

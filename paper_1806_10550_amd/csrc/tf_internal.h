@@ -82,6 +82,9 @@ struct PassParams {
     unsigned long long *res_clear;  // slot zeroed by block 0 (may be null)
     int res_spread;                 // copies of the reduction record in a slot (>= 1)
     int tiles_x, tiles_y;
+    // x solve only, nullable: per tile (ty * tiles_x + tx) the compensated sum {s, c} and the
+    // minimum of the u_{k+1} cells it writes (the mass diagnostic of the iterate, 4 doubles)
+    double *mass;
 };
 
 struct ChainParams {
@@ -144,6 +147,9 @@ hipError_t launch_flux_divergence(int nx, int ny, double ids, double ids2, const
                                   const double *u, double alpha, double beta, const double *add,
                                   double *out, hipStream_t s);
 hipError_t launch_mass(const double *u, size_t n, double *partials, int nblocks, hipStream_t s);
+// Combine ntiles per-tile mass records {s, c, min, -} (PassParams::mass) in a fixed order into
+// out = {sum, min}.
+hipError_t launch_mass_tiles(const double *part, int ntiles, double *out, hipStream_t s);
 hipError_t launch_pass_ens(int dir, bool solve, int km, const EnsParams &e, hipStream_t s);
 // b^n of every active film at the first iteration of an attempt (items: the y-sweep tiles)
 hipError_t launch_bn_ens(const EnsParams &e, hipStream_t s);

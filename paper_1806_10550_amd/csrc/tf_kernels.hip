@@ -472,6 +472,9 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
         }
         __syncthreads();
         double emax = 0.0;
+        // mass diagnostic of the iterate (wave-uniform switch): compensated sum and minimum
+        const bool diag = p.mass != nullptr;
+        double ms = 0.0, mc = 0.0, mmin = __builtin_inf();
 #pragma unroll
         for (int r = 0; r < TILE / NSUB; ++r) {
             const int ly = wave + NSUB * r;
@@ -482,6 +485,10 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
                 emax = fmax(emax, fabs(v) * rcp(fabs(uk)));
                 if (!(un > 0.0)) flags |= (un != un || v != v) ? FLAG_NAN : FLAG_NONPOS;
                 (p.out + (size_t)(y0 + ly) * nx + x0)[(unsigned)lane] = un;
+                if (diag) {
+                    two_sum_acc(ms, mc, un);
+                    mmin = fmin(mmin, un);
+                }
             }
         }
         const double wm = wave_max(emax);
@@ -490,6 +497,34 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
             unsigned long long *rs = p.res + (size_t)((blockIdx.x * NSUB + wave) % p.res_spread) * RES_WORDS;
             atomicMax(&rs[RES_EMAX], (unsigned long long)__double_as_longlong(wm));
             if (wf) atomicOr(&rs[RES_FLAGS], (unsigned long long)wf);
+        }
+        if (diag) {
+            // fixed-order butterfly over the lanes, then the four waves in order: the tile's
+            // record does not depend on scheduling
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                comp_add(ms, mc, __shfl_xor(ms, o), __shfl_xor(mc, o));
+                mmin = fmin(mmin, __shfl_xor(mmin, o));
+            }
+            __syncthreads(); // the output tile is no longer read
+            if (lane == 0) {
+                sB[3 * wave] = ms;
+                sB[3 * wave + 1] = mc;
+                sB[3 * wave + 2] = mmin;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double s = sB[0], c = sB[1], m = sB[2];
+                for (int w = 1; w < NSUB; ++w) {
+                    comp_add(s, c, sB[3 * w], sB[3 * w + 1]);
+                    m = fmin(m, sB[3 * w + 2]);
+                }
+                double *o = p.mass + 4 * ((size_t)ty * p.tiles_x + tx);
+                o[0] = s;
+                o[1] = c;
+                o[2] = m;
+                o[3] = 0.0;
+            }
         }
     }
 }
@@ -885,13 +920,6 @@ __global__ void __launch_bounds__(256) k_bn_ens(EnsParams e)
 // Mass diagnostic: per-block compensated (Neumaier) sum, minimum and NaN flag, reduced
 // in a fixed tree order; the host adds the block records in index order.
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ void two_sum_acc(double &s, double &c, double x)
-{
-    const double t = s + x;
-    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-    s = t;
-}
-
 __global__ void __launch_bounds__(256) k_mass(const double *u, size_t n, double *partials)
 {
     __shared__ double ss[256], sc[256], sm[256], sn[256];
@@ -923,6 +951,34 @@ __global__ void __launch_bounds__(256) k_mass(const double *u, size_t n, double 
     }
 }
 
+
+// Per-tile mass records of the x solve combined in a fixed order (strided per thread, then
+// a tree): out = {sum, min}.
+__global__ void __launch_bounds__(256) k_mass_tiles(const double *part, int ntiles, double *out)
+{
+    __shared__ double ss[256], sc[256], sm[256];
+    double s = 0.0, c = 0.0, m = __builtin_inf();
+    for (int i = threadIdx.x; i < ntiles; i += 256) {
+        comp_add(s, c, part[4 * (size_t)i], part[4 * (size_t)i + 1]);
+        m = fmin(m, part[4 * (size_t)i + 2]);
+    }
+    ss[threadIdx.x] = s; sc[threadIdx.x] = c; sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            double a = ss[threadIdx.x], ca = sc[threadIdx.x];
+            comp_add(a, ca, ss[threadIdx.x + w], sc[threadIdx.x + w]);
+            ss[threadIdx.x] = a;
+            sc[threadIdx.x] = ca;
+            sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = ss[0] + sc[0];
+        out[1] = sm[0];
+    }
+}
 
 // ------------------------------------------------------------------------------------
 // Ensemble control (Fig. FlowChartTime per film, on the device). One block; after
@@ -1143,6 +1199,12 @@ int mass_blocks(size_t n)
 hipError_t launch_mass(const double *u, size_t n, double *partials, int nblocks, hipStream_t s)
 {
     k_mass<<<dim3(nblocks), dim3(256), 0, s>>>(u, n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_mass_tiles(const double *part, int ntiles, double *out, hipStream_t s)
+{
+    k_mass_tiles<<<dim3(1), dim3(256), 0, s>>>(part, ntiles, out);
     return hipGetLastError();
 }
 

