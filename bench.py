@@ -32,9 +32,10 @@ HBM_PEAK_GBS = 8000.0
 # write w, the x sweep read u_k and w and write u_{k+1}, each once: 48 B.
 ALGO_BYTES_PER_CELL_ITERATION = 48.0
 # The bytes of each kernel class taken alone (the inputs it reads, the field it writes).
-ALGO_BYTES_PER_CELL = {"relations_y": 16, "solve_y": 24, "relations_x": 16, "solve_x": 24}
+ALGO_BYTES_PER_CELL = {"relations_y": 16, "solve_y": 24, "relations_x": 16, "solve_x": 24, "xrow": 24}
 KERNEL_SOURCES = ["paper_1806_10550_amd/csrc/tf_kernels.hip", "paper_1806_10550_amd/csrc/tf_internal.h",
-                  "paper_1806_10550_amd/csrc/tf_device.h"]
+                  "paper_1806_10550_amd/csrc/tf_device.h", "paper_1806_10550_amd/csrc/tf_sweep.h",
+                  "paper_1806_10550_amd/csrc/tf_xrow.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large8192.json")
 
 
@@ -84,7 +85,8 @@ def iteration_traffic(ncells):
     if t.get("kernel_hash") != kernel_hash():
         return None
     ks = t.get("kernels", {})
-    per = {"relations_y": 1, "solve_y": 1, "relations_x": 1, "solve_x": 1, "chain": 2}
+    per = {"relations_y": 1, "solve_y": 1, "chain": 1}
+    per.update({"xrow": 1} if "xrow" in ks else {"relations_x": 1, "solve_x": 1, "chain": 2})
     if any(k not in ks for k in per):
         return None
     return sum(n * (ks[k]["fetch_kib"] + ks[k]["write_kib"]) * 1024.0 * t.get("copy_scale", 1.0)
@@ -159,6 +161,7 @@ def bench_ensemble(args):
     h0 = [synth.noise_film(f.n, f.n, f.seed, 1.0, 0.01) for f in films]
     dev = torch.device("cuda:0")
     ens = Ensemble(nx, nx, ds, kap)
+    ens.set_xsweep(args.xsweep)
     scheme = dict(tol=1e-10, max_newton=10, adaptive=1, dt_min=1e-9, dt_max=1.0, dt_shrink=0.5, dt_grow=1.1,
                   grow_after=5)
     ens.set_scheme(**scheme)
@@ -180,6 +183,7 @@ def bench_ensemble(args):
         g = Grid(nx[f], nx[f], ds[f])
         g.set_model(kap[f], 0.1, 3, 2)
         g.set_scheme(**scheme)
+        g.set_xsweep(ens.xsweep(f))  # the variant the ensemble gives this film
         h = torch.from_numpy(h0[f]).to(dev)
         g.bind(h)
         dtf = 0.1
@@ -204,6 +208,7 @@ def bench_ensemble(args):
                                   f"L=8 lambda_m, noise 0.01 (default_rng(3)), backward Euler, adaptive dt from 0.1 "
                                   f"(K=10), tol 1e-10",
                       "cells": cells},
+           "xsweep": {v: sum(ens.xsweep(f) == v for f in range(len(films))) for v in ("row", "partitioned")},
            "ensemble_s": t_ens, "loop_s": t_loop, "loop_over_ensemble": t_loop / t_ens,
            "newton_iters_total": int(sum(its)), "loop_newton_iters_total": loop_iters,
            "bitwise_equal_to_loop": bool(same), "status_ok": st == 0,
@@ -333,6 +338,8 @@ def main():
                          "adjoint: 512^2 gradient by the checkpointed adjoint; "
                          "spectrum: radial Fourier transform of a 4000^2 film")
     ap.add_argument("--films", type=int, default=256)
+    ap.add_argument("--xsweep", default="auto", choices=["auto", "row", "partitioned"],
+                    help="ensemble workload: x-sweep line solver of the films (auto: each as alone)")
     ap.add_argument("--model", default="power", choices=["power", "nlc", "polymer"],
                     help="single workload only: the power law of the default workload, or the NLC "
                          "(H0 = 0.5) / polymer (H0 = 3.9) film on the same grid with L = 256 lambda_m "
@@ -447,13 +454,16 @@ def main():
     # y and x sweeps) as a unit: 48 algorithmic bytes per cell per iteration (each sweep reads
     # its two inputs and writes its output once) over their mean time per iteration from the
     # per-launch HIP events of the profiled run.
-    sweep = ["relations_y", "chain_y", "solve_y", "relations_x", "chain_x", "solve_x"]
+    # the kernels of one iteration: the y sweep's three, then the x sweep's (one whole-row
+    # kernel, or three with the partitioned variant)
+    sweep = ["relations_y", "chain_y", "solve_y"] + (
+        ["xrow"] if prof.get("xrow", (0, 0))[1] else ["relations_x", "chain_x", "solve_x"])
     iter_kernel_s = sum(prof[k][0] for k in sweep) / 1e3 / total_iters
     achieved = ALGO_BYTES_PER_CELL_ITERATION * ncells / iter_kernel_s / 1e9
     traffic = iteration_traffic(ncells) if args.model == "power" else None
     kernel_ms = sum(v[0] for v in prof.values())
     iter_frac = (ALGO_BYTES_PER_CELL_ITERATION * ncells * total_iters) / (elapsed * HBM_PEAK_GBS * 1e9)
-    dom = max(ALGO_BYTES_PER_CELL, key=lambda k: prof[k][0])
+    dom = max((k for k in ALGO_BYTES_PER_CELL if k in prof), key=lambda k: prof[k][0])
     dom_s = prof[dom][0] / 1e3 / max(prof[dom][1], 1)
 
     out = {

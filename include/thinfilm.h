@@ -115,8 +115,29 @@ tf_status tf_set_model_polymer(tf_grid *g, double C, double Cst, double Aox, dou
 tf_status tf_model_coeffs(tf_grid *g, const double *h, int n, double *out);
 tf_status tf_set_scheme(tf_grid *g, const tf_scheme *s);
 tf_status tf_get_scheme(const tf_grid *g, tf_scheme *s);
-/* 1: fill tf_step_info.mass / hmin after every accepted step (one extra read of h). */
+/* 1: fill tf_step_info.mass / hmin after every accepted step (Sec. "Conservation of
+ * Mass"): the x sweep forms a compensated partial sum and minimum of each iterate as it
+ * stores it, and the accepted iterate's records are combined in a fixed order (no extra
+ * read of h). */
 tf_status tf_set_diagnostics(tf_grid *g, int mass_every_step);
+
+/* Line-solver variant of the x sweep (eqs. JacobianSystem2-3: one pentadiagonal system
+ * per grid row, then u_{k+1} = u_k + v and the update ratio of eq. NewtonError). Both give
+ * the same Newton root; they differ in rounding, so iterates agree to ~1e-13 relative.
+ *   TF_XSWEEP_PARTITIONED  three kernels per sweep: segment relations of 64-cell tiles,
+ *                          the interface chain of each row, then the segment solves
+ *                          (any nx);
+ *   TF_XSWEEP_ROW          one kernel: a workgroup holds whole rows, eliminates 16-cell
+ *                          sub-segments per lane and couples them by a tree of merges in
+ *                          LDS (4 <= nx <= 8192);
+ *   TF_XSWEEP_AUTO         the row kernel when nx allows it (the default at tf_create).
+ * TF_EINVAL for an unknown variant or TF_XSWEEP_ROW with nx > 8192. tf_get_xsweep returns
+ * the variant in use (-1 for a NULL grid). */
+#define TF_XSWEEP_AUTO (-1)
+#define TF_XSWEEP_PARTITIONED 0
+#define TF_XSWEEP_ROW 1
+tf_status tf_set_xsweep(tf_grid *g, int variant);
+int tf_get_xsweep(const tf_grid *g);
 
 /* Borrow the caller's state h (device, nx*ny FP64). The library reads and writes it
  * in place; during a call it may also hold iterates there. It must stay allocated
@@ -183,6 +204,14 @@ tf_status tf_ensemble_set_model_polymer(tf_ensemble *e, double C, double Cst, do
 tf_status tf_ensemble_destroy(tf_ensemble *e);
 /* scheme as for tf_set_scheme (theta in [0.5, 1]; theta < 1 allocates one packed field) */
 tf_status tf_ensemble_set_scheme(tf_ensemble *e, const tf_scheme *s);
+/* x-sweep line solver of every film (see tf_set_xsweep): TF_XSWEEP_AUTO gives film f the
+ * variant tf_xsweep_choice(nx_f, rows of all films) (the default at creation); TF_XSWEEP_ROW the
+ * whole-row kernel for every film whose rows fit a 4-wave workgroup (nx <= 4096; the others
+ * stay partitioned); TF_XSWEEP_PARTITIONED the partitioned solver for all. The whole-row
+ * films of an ensemble share one launch per iteration. tf_ensemble_xsweep returns a film's
+ * variant (0 partitioned, 1 whole-row; -1 for a bad film index). */
+tf_status tf_ensemble_set_xsweep(tf_ensemble *e, int variant);
+int tf_ensemble_xsweep(const tf_ensemble *e, int film);
 /* total number of cells (length of the packed buffer) */
 long long tf_ensemble_size(const tf_ensemble *e);
 /* host array of nfilms offsets (in doubles) of each film in the packed buffer */
@@ -277,6 +306,20 @@ tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *r
 tf_status tf_autotune(int length, int batch, int transposed, const char *cache_path);
 tf_status tf_autotune_load(const char *cache_path);
 int tf_autotune_choice(int length, int batch, int transposed);
+/* Forward x sweep (eqs. JacobianSystem2-3 per grid row; see tf_set_xsweep): time both
+ * variants -- partitioned (3 kernels) and whole-row (1 kernel, rows of at most 8192 cells)
+ * -- on a film of `batch` rows of `length` cells (1 + 0.01 noise, the n = 3, m = 2 power law
+ * with kappa = 10, b = 0.1, ds = 0.67347, dt = 0.2; median of 5 timed runs after a warm-up),
+ * remember the faster for films of similar shape and append {arch, kind: "xsweep", length,
+ * batch, variant, ms: {...}} to cache_path (nullable; tf_autotune_load reads these lines
+ * too). TF_EINVAL for length or batch below 4. Grids (tf_create) and ensembles
+ * (tf_ensemble_create, per film, with ny = the rows of all its films, since its x sweep is one
+ * launch over all of them) take the variant tf_xsweep_choice(nx, ny) returns at creation: the
+ * tuned entry of the nearest shape (log distance below 0.7), else the whole-row kernel when
+ * the launch has at most 2048 rows; never the whole-row kernel for rows above 4096 cells.
+ * Returns 0 (partitioned) or 1 (whole-row). */
+tf_status tf_autotune_xsweep(int length, int batch, const char *cache_path);
+int tf_xsweep_choice(int nx, int ny);
 
 /* Description of the calling thread's most recent error (never NULL). */
 const char *tf_last_error(void);

@@ -18,16 +18,20 @@ from .lib import Grid, load_shipped_tuning
 
 
 # Grids (and with them their device scratch and adjoint buffers) are reused across
-# rollouts of the same geometry; every forward and backward pass sets the model and the
-# scheme it needs before using one.
+# rollouts of the same geometry on the same stream; every forward and backward pass sets
+# the model and the scheme it needs before using one. A grid enqueues its work on the torch
+# stream that was current when it was created, so the key holds that stream too: the
+# tensor copies of a rollout (checkpoint clones, restores) then run in order with the
+# library's launches.
 _grids = {}
 
 
 def _grid(nx, ny, ds):
-    key = (nx, ny, float(ds))
+    stream = torch.cuda.current_stream()
+    key = (nx, ny, float(ds), stream.device.index, stream.cuda_stream)
     g = _grids.get(key)
     if g is None:
-        g = _grids[key] = Grid(nx, ny, ds)
+        g = _grids[key] = Grid(nx, ny, ds, stream=stream)
     return g
 
 

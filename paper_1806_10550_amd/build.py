@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libthinfilm.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["tf_kernels.hip", "tf_api.hip", "tf_ensemble.hip", "tf_adjoint.hip", "tf_spectrum.hip"]
+SOURCES = ["tf_kernels.hip", "tf_xrow.hip", "tf_api.hip", "tf_ensemble.hip", "tf_adjoint.hip", "tf_spectrum.hip"]
 LIBS = ["-lhipfft"]
 
 FLAGS = [

@@ -579,6 +579,21 @@ __global__ void k_fill_test(size_t n, double *bands, double *rhs)
     }
 }
 
+// A film 1 + 0.01 r and a right-hand side 1e-6 (r - 1/2), r uniform in [0, 1) from a
+// counter-based hash, for timing the forward x sweeps.
+__global__ void k_fill_film(size_t n, double *u, double *w)
+{
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
+        unsigned long long z = k * 0x9E3779B97F4A7C15ull + 0x2545F4914F6CDD1Dull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const double r = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+        u[k] = 1.0 + 0.01 * r;
+        w[k] = 1e-6 * (r - 0.5);
+    }
+}
+
 } // namespace tf
 
 // =========================================================================================
@@ -623,6 +638,9 @@ TuneTable &tune_table()
     static TuneTable t;
     return t;
 }
+// Table entries of the forward x sweep (variant 0: partitioned, 1: whole-row) use this
+// value in TuneKey::transposed.
+constexpr int XSWEEP_KIND = 2;
 
 // choice for a batch of `nl` lines of length `np` (plain or transposed solves): the
 // autotuned entry of the same kind with the nearest (log-distance) shape, else a
@@ -636,7 +654,7 @@ Choice pick_variant(int np, int nl, bool trans)
     Choice c;
     bool found = false;
     for (auto &kv : t.best) {
-        if (kv.first.transposed != (int)trans) continue;
+        if (kv.first.transposed != (int)trans) continue; // (also skips the x-sweep entries)
         const double d = std::fabs(std::log((double)kv.first.length / np)) + std::fabs(std::log((double)kv.first.batch / nl));
         if (d < best_d) { best_d = d; c = kv.second; found = true; }
     }
@@ -649,6 +667,33 @@ Choice pick_variant(int np, int nl, bool trans)
 struct Scratch {
     double *rel = nullptr, *ext = nullptr, *chain = nullptr, *work = nullptr;
 };
+
+} // namespace
+
+namespace tf {
+// x-sweep variant for ny rows of nx cells in one launch: the tuned entry with the nearest
+// shape, else the measured rule (the whole-row kernel while the launch has at most 2048
+// rows: with few rows the partitioned solver's three launches are latency bound, with many
+// its tile kernels stream faster); the whole-row kernel is only chosen where its 4-wave
+// workgroups hold the row (nx <= 4096).
+int xsweep_choice(int nx, int ny)
+{
+    if (!xrow_supported(nx) || nx > XR_ROW4_MAX_NX) return 0;
+    TuneTable &t = tune_table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    double best_d = 1e30;
+    int v = -1;
+    for (auto &kv : t.best) {
+        if (kv.first.transposed != XSWEEP_KIND) continue;
+        const double d = std::fabs(std::log((double)kv.first.length / nx)) + std::fabs(std::log((double)kv.first.batch / ny));
+        if (d < best_d) { best_d = d; v = kv.second.variant; }
+    }
+    if (v >= 0 && best_d < 0.7) return v;
+    return ny <= 2048 ? 1 : 0;
+}
+} // namespace tf
+
+namespace {
 
 // rowio: rhs and out line-major (partitioned variant, transposed MODE 0 solves only).
 tf_status sb_solve(Choice ch, bool trans, int mode, int nl, int np, const double *bands, const double *rhs,
@@ -1052,6 +1097,118 @@ tf_status tf_autotune(int length, int batch, int transposed, const char *cache_p
     return TF_OK;
 }
 
+tf_status tf_autotune_xsweep(int length, int batch, const char *cache_path)
+{
+    if (length < 4 || batch < 4) return afail(TF_EINVAL, "need length >= 4 and batch >= 4");
+    const size_t N = (size_t)length * batch;
+    const size_t recs = (size_t)tf::seg_count(length) * batch;
+    double *u = nullptr, *w = nullptr, *out = nullptr, *rel = nullptr, *ext = nullptr, *chain = nullptr;
+    unsigned long long *res = nullptr;
+    hipStream_t s = nullptr;
+    bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess
+              && hipMalloc(&u, N * sizeof(double)) == hipSuccess && hipMalloc(&w, N * sizeof(double)) == hipSuccess
+              && hipMalloc(&out, N * sizeof(double)) == hipSuccess
+              && hipMalloc(&rel, recs * tf::NREL * sizeof(double)) == hipSuccess
+              && hipMalloc(&ext, recs * tf::NEXT * sizeof(double)) == hipSuccess
+              && hipMalloc(&chain, recs * tf::NCHAIN * sizeof(double)) == hipSuccess
+              && hipMalloc(&res, tf::RES_SPREAD * tf::RES_WORDS * sizeof(unsigned long long)) == hipSuccess;
+    tf_status st = ok ? TF_OK : afail(TF_ENOMEM, "autotune allocation failed");
+    // the n = 3, m = 2 power law of the benchmark films (kappa = 10, b = 0.1), ds = 0.67347,
+    // backward Euler dt = 0.2
+    tf::Model M{};
+    M.kappa = 10.0; M.b = 0.1; M.n = 3; M.m = 2;
+    M.Cn = 10.0 * 3.0 * 1e-3; M.Cm = 10.0 * 2.0 * 1e-2; M.Dn = 10.0 * 3.0 * 1.0 * 1e-3; M.Dm = 0.0;
+    M.p32 = true; M.kind = tf::MODEL_POWER; M.cap = 1.0;
+    tf::PassParams P{};
+    const double ds = 0.67347, dt = 0.2;
+    P.nx = length; P.ny = batch;
+    P.ids2 = 1.0 / (ds * ds);
+    P.f0s = P.ids2;
+    P.ka = 0.5 * dt * P.ids2;
+    P.K0 = 3.0 * P.ka * P.ids2;
+    P.K1 = P.ka * M.Dn;
+    P.M = M;
+    P.res_spread = tf::RES_SPREAD;
+    P.u = u; P.in2 = w; P.out = out; P.rel = rel; P.ext = ext; P.res = res;
+    P.tiles_x = tf::seg_count(length);
+    P.tiles_y = (batch + tf::TILE - 1) / tf::TILE;
+    const tf::ChainParams C{batch, tf::seg_count(length), rel, chain, ext};
+    auto run = [&](int v) -> hipError_t {
+        if (v == 1) return tf::launch_xrow(P, s);
+        tf::PassParams Q = P;
+        Q.res = nullptr;
+        hipError_t e = tf::launch_pass(1, false, Q, s);
+        if (e == hipSuccess) e = tf::launch_chain(C, s);
+        if (e == hipSuccess) e = tf::launch_pass(1, true, P, s);
+        return e;
+    };
+    const int nv = tf::xrow_supported(length) ? 2 : 1;
+    const char *names[2] = {"partitioned", "row"};
+    double ms[2] = {1e30, 1e30};
+    if (st == TF_OK) {
+        tf::k_fill_film<<<dim3(1024), dim3(256), 0, s>>>(N, u, w);
+        (void)hipMemsetAsync(res, 0, tf::RES_SPREAD * tf::RES_WORDS * sizeof(unsigned long long), s);
+        hipEvent_t a, b;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        for (int v = 0; v < nv && st == TF_OK; ++v) {
+            std::vector<float> t;
+            for (int r = 0; r < 6 && st == TF_OK; ++r) {
+                (void)hipEventRecord(a, s);
+                const hipError_t e = run(v);
+                (void)hipEventRecord(b, s);
+                if (e != hipSuccess) {
+                    st = afail(TF_EDEVICE, std::string("x-sweep launch: ") + hipGetErrorString(e));
+                    break;
+                }
+                (void)hipEventSynchronize(b);
+                float el = 0.0f;
+                (void)hipEventElapsedTime(&el, a, b);
+                if (r > 0) t.push_back(el); // first run is a warm-up
+            }
+            std::sort(t.begin(), t.end());
+            ms[v] = t.empty() ? 1e30 : t[t.size() / 2];
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        if (st == TF_OK && hipStreamSynchronize(s) != hipSuccess) st = afail(TF_EDEVICE, "x-sweep timing failed");
+    }
+    (void)hipFree(u);
+    (void)hipFree(w);
+    (void)hipFree(out);
+    (void)hipFree(rel);
+    (void)hipFree(ext);
+    (void)hipFree(chain);
+    (void)hipFree(res);
+    if (s) (void)hipStreamDestroy(s);
+    if (st != TF_OK) return st;
+    const int best = (nv > 1 && ms[1] < ms[0]) ? 1 : 0;
+    {
+        TuneTable &t = tune_table();
+        std::lock_guard<std::mutex> lk(t.mu);
+        Choice c;
+        c.variant = best;
+        t.best[{length, batch, XSWEEP_KIND}] = c;
+    }
+    if (cache_path != nullptr && cache_path[0] != '\0') {
+        std::ofstream f(cache_path, std::ios::app);
+        if (!f) return afail(TF_EINVAL, std::string("cannot write ") + cache_path);
+        std::ostringstream o;
+        o << "{\"arch\": \"" << arch_name() << "\", \"kind\": \"xsweep\", \"length\": " << length
+          << ", \"batch\": " << batch << ", \"variant\": \"" << names[best] << "\", \"ms\": {";
+        char buf[64];
+        for (int v = 0; v < nv; ++v) {
+            std::snprintf(buf, sizeof buf, "%.6f", ms[v]);
+            o << (v ? ", " : "") << "\"" << names[v] << "\": " << buf;
+        }
+        o << "}}\n";
+        f << o.str();
+    }
+    return TF_OK;
+}
+
+int tf_xsweep_choice(int nx, int ny) { return tf::xsweep_choice(nx, ny); }
+
 tf_status tf_autotune_load(const char *cache_path)
 {
     if (cache_path == nullptr) return afail(TF_EINVAL, "NULL path");
@@ -1081,6 +1238,12 @@ tf_status tf_autotune_load(const char *cache_path)
         const std::string Tr = field("transposed");
         if (L.empty() || Bt.empty()) continue;
         Choice c;
+        if (field("kind") == "xsweep") {
+            c.variant = V == "row" ? 1 : 0;
+            t.best[{std::stoi(L), std::stoi(Bt), XSWEEP_KIND}] = c;
+            ++loaded;
+            continue;
+        }
         c.variant = V == "thomas" ? V_THOMAS : (V == "pcr" ? V_PCR : V_PARTITIONED);
         c.block = Bs.empty() ? 64 : std::stoi(Bs);
         t.best[{std::stoi(L), std::stoi(Bt), Tr.empty() ? 0 : (std::stoi(Tr) != 0)}] = c;

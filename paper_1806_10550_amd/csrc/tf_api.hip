@@ -35,8 +35,8 @@ tf_status fail(tf_status s, const std::string &msg)
         if (e_ != hipSuccess) return fail(TF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-enum ProfKind { P_REL_Y, P_CHAIN_Y, P_SOLVE_Y, P_REL_X, P_CHAIN_X, P_SOLVE_X, P_RHS, P_MASS, P_NKIND };
-const char *kProfNames = "relations_y,chain_y,solve_y,relations_x,chain_x,solve_x,rhs_theta,mass";
+enum ProfKind { P_REL_Y, P_CHAIN_Y, P_SOLVE_Y, P_REL_X, P_CHAIN_X, P_SOLVE_X, P_RHS, P_MASS, P_XROW, P_NKIND };
+const char *kProfNames = "relations_y,chain_y,solve_y,relations_x,chain_x,solve_x,rhs_theta,mass,xrow";
 
 constexpr int RES_SLOTS = 4;
 constexpr int RES_STRIDE = tf::RES_SPREAD * tf::RES_WORDS; // words per reduction slot
@@ -129,6 +129,7 @@ struct tf_grid {
     double *mout = nullptr;    // {sum, min} combined from mpart
     unsigned long long *res = nullptr, *hres = nullptr;
     int Px = 0, Py = 0;
+    int xsweep = TF_XSWEEP_PARTITIONED; // x-sweep variant (TF_XSWEEP_*)
     long iter = 0;
     int successes = 0;
     double t = 0.0;
@@ -221,6 +222,12 @@ tf_status enqueue_iteration(tf_grid *g, const double *bnp, const double *uk, dou
     P.out = ukp1;
     P.tiles_x = g->Px;
     P.tiles_y = (g->ny + tf::TILE - 1) / tf::TILE;
+    if (g->xsweep == TF_XSWEEP_ROW) {
+        // one whole-row kernel: assembly, elimination, in-row tree, back-substitution, update
+        P.res = res;
+        P.mass = diag ? g->mpart : nullptr;
+        return timed(g, P_XROW, [&] { return tf::launch_xrow(P, g->stream); });
+    }
     if ((st = timed(g, P_REL_X, [&] { return tf::launch_pass(1, false, P, g->stream); })) != TF_OK) return st;
     tf::ChainParams Cx{g->ny, g->Px, g->rel, g->chain, g->ext};
     if ((st = timed(g, P_CHAIN_X, [&] { return tf::launch_chain(Cx, g->stream); })) != TF_OK) return st;
@@ -288,12 +295,17 @@ tf_status mass_of(tf_grid *g, const double *u, double *mass, double *hmin, bool 
 }
 
 int x_tiles(const tf_grid *g) { return g->Px * ((g->ny + tf::TILE - 1) / tf::TILE); }
+// Mass records the x sweep leaves (one per x-solve tile or per whole-row workgroup).
+int mass_records(const tf_grid *g)
+{
+    return g->xsweep == TF_XSWEEP_ROW ? tf::xrow_blocks(g->nx, g->ny) : x_tiles(g);
+}
 
 // Mass and minimum of the last iterate from the records its x solve left per tile (Sec.
 // "Conservation of Mass"), combined on the device in a fixed order: no extra read of h.
 tf_status fused_mass(tf_grid *g, double *mass, double *hmin)
 {
-    tf_status st = timed(g, P_MASS, [&] { return tf::launch_mass_tiles(g->mpart, x_tiles(g), g->mout, g->stream); });
+    tf_status st = timed(g, P_MASS, [&] { return tf::launch_mass_tiles(g->mpart, mass_records(g), g->mout, g->stream); });
     if (st != TF_OK) return st;
     TF_HIP(hipMemcpyAsync(g->hpart, g->mout, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
     TF_HIP(hipStreamSynchronize(g->stream));
@@ -460,6 +472,7 @@ tf_status tf_create(int nx, int ny, double ds, void *stream, tf_grid **out)
     g->S = tf_scheme{1.0, 1e-10, 1e-6, 1.0, 0.5, 1.1, 5000, 5, 0};
     g->Px = tf::seg_count(nx);
     g->Py = tf::seg_count(ny);
+    g->xsweep = tf::xsweep_choice(nx, ny) == 1 ? TF_XSWEEP_ROW : TF_XSWEEP_PARTITIONED;
     if (hipGetDevice(&g->device) != hipSuccess) {
         delete g;
         return fail(TF_EDEVICE, "hipGetDevice failed");
@@ -473,7 +486,8 @@ tf_status tf_create(int nx, int ny, double ds, void *stream, tf_grid **out)
               && hipMalloc(&g->ext, lines_seg * tf::NEXT * sizeof(double)) == hipSuccess
               && hipMalloc(&g->chain, lines_seg * tf::NCHAIN * sizeof(double)) == hipSuccess
               && hipMalloc(&g->partials, 4096 * 4 * sizeof(double)) == hipSuccess
-              && hipMalloc(&g->mpart, (size_t)x_tiles(g) * 4 * sizeof(double)) == hipSuccess
+              && hipMalloc(&g->mpart, (size_t)std::max(x_tiles(g), tf::xrow_supported(nx) ? tf::xrow_blocks(nx, ny) : 0)
+                                          * 4 * sizeof(double)) == hipSuccess
               && hipMalloc(&g->mout, 2 * sizeof(double)) == hipSuccess
               && hipMalloc(&g->res, RES_SLOTS * RES_STRIDE * sizeof(unsigned long long)) == hipSuccess
               && hipHostMalloc(&g->hres, RES_STRIDE * sizeof(unsigned long long), hipHostMallocDefault) == hipSuccess
@@ -593,6 +607,21 @@ tf_status tf_get_scheme(const tf_grid *g, tf_scheme *s)
     *s = g->S;
     return TF_OK;
 }
+
+tf_status tf_set_xsweep(tf_grid *g, int variant)
+{
+    if (g == nullptr) return fail(TF_EINVAL, "grid is NULL");
+    if (variant == TF_XSWEEP_AUTO)
+        variant = tf::xsweep_choice(g->nx, g->ny) == 1 ? TF_XSWEEP_ROW : TF_XSWEEP_PARTITIONED;
+    if (variant != TF_XSWEEP_PARTITIONED && variant != TF_XSWEEP_ROW)
+        return fail(TF_EINVAL, "unknown x-sweep variant");
+    if (variant == TF_XSWEEP_ROW && !tf::xrow_supported(g->nx))
+        return fail(TF_EINVAL, "the whole-row x sweep needs 4 <= nx <= " + std::to_string(tf::XR_MAX_NX));
+    g->xsweep = variant;
+    return TF_OK;
+}
+
+int tf_get_xsweep(const tf_grid *g) { return g == nullptr ? -1 : g->xsweep; }
 
 tf_status tf_set_diagnostics(tf_grid *g, int mass_every_step)
 {

@@ -42,10 +42,13 @@ struct tf_ensemble {
     tf_scheme S{};
     std::vector<tf::FilmDesc> desc;
     long long ncells = 0, nrec = 0;
-    int ny_items = 0, nx_items = 0, ncy_items = 0, ncx_items = 0;
+    int ny_items = 0, nx_items = 0, ncy_items = 0, ncx_items = 0, nxr_items = 0;
     tf::FilmDesc *d_desc = nullptr;
     tf::FilmState *d_state = nullptr, *h_state = nullptr;
-    int *d_items = nullptr;  // [y tiles | x tiles | y chain blocks | x chain blocks]
+    // [y tiles | x tiles | y chain blocks | x chain blocks | whole-row blocks]; the x tiles and
+    // x chain blocks cover the films whose x sweep is partitioned, the row blocks the others
+    int *d_items = nullptr;
+    std::vector<int> xsweep;  // per film: 1 = whole-row x sweep, 0 = partitioned
     int *d_active = nullptr, *h_active = nullptr;
     double *buf0 = nullptr, *buf1 = nullptr, *buf2 = nullptr, *w = nullptr;
     double *rel = nullptr, *ext = nullptr, *chain = nullptr;
@@ -73,11 +76,13 @@ tf::EnsParams params(const tf_ensemble *e, int which)
     p.bn = e->bn;
     p.theta = e->S.theta;
     const int off_y = 0, off_x = 3 * e->ny_items, off_cy = off_x + 3 * e->nx_items, off_cx = off_cy + 2 * e->ncy_items;
+    const int off_xr = off_cx + 2 * e->ncx_items;
     switch (which) {
     case 0: p.items = e->d_items + off_y; p.nitems = e->ny_items; break;
     case 1: p.items = e->d_items + off_x; p.nitems = e->nx_items; break;
     case 2: p.items = e->d_items + off_cy; p.nitems = e->ncy_items; break;
-    default: p.items = e->d_items + off_cx; p.nitems = e->ncx_items; break;
+    case 3: p.items = e->d_items + off_cx; p.nitems = e->ncx_items; break;
+    default: p.items = e->d_items + off_xr; p.nitems = e->nxr_items; break;
     }
     return p;
 }
@@ -90,9 +95,12 @@ tf_status enqueue_iteration(tf_ensemble *e)
     TF_EHIP(tf::launch_pass_ens(0, false, e->km, params(e, 0), e->stream));
     TF_EHIP(tf::launch_chain_ens(params(e, 2), 0, e->stream));
     TF_EHIP(tf::launch_pass_ens(0, true, e->km, params(e, 0), e->stream));
-    TF_EHIP(tf::launch_pass_ens(1, false, e->km, params(e, 1), e->stream));
-    TF_EHIP(tf::launch_chain_ens(params(e, 3), 1, e->stream));
-    TF_EHIP(tf::launch_pass_ens(1, true, e->km, params(e, 1), e->stream));
+    if (e->nx_items > 0) {
+        TF_EHIP(tf::launch_pass_ens(1, false, e->km, params(e, 1), e->stream));
+        TF_EHIP(tf::launch_chain_ens(params(e, 3), 1, e->stream));
+        TF_EHIP(tf::launch_pass_ens(1, true, e->km, params(e, 1), e->stream));
+    }
+    if (e->nxr_items > 0) TF_EHIP(tf::launch_xrow_ens(e->km, params(e, 4), e->stream));
     TF_EHIP(tf::launch_ens_control(e->d_state, e->nfilms, S, e->d_active, e->stream));
     return TF_OK;
 }
@@ -134,6 +142,60 @@ tf_status set_all_models(tf_ensemble *e, const tf::Model &M, int km)
     return TF_OK;
 }
 
+// Work lists of one iteration (see tf_ensemble::d_items); the x sweep of film f is
+// whole-row when xsweep[f] == 1.
+void build_items(tf_ensemble *e, std::vector<int> &items)
+{
+    std::vector<int> items_y, items_x, items_cy, items_cx, items_xr;
+    for (int f = 0; f < e->nfilms; ++f) {
+        const tf::FilmDesc &d = e->desc[f];
+        const int tyx = (d.nx + tf::LT0 - 1) / tf::LT0;
+        for (int ty = 0; ty < d.Py; ++ty)
+            for (int tx = 0; tx < tyx; ++tx) { items_y.push_back(f); items_y.push_back(tx); items_y.push_back(ty); }
+        for (int lb = 0; lb < (d.nx + 63) / 64; ++lb) { items_cy.push_back(f); items_cy.push_back(lb); }
+        if (e->xsweep[f] == 1) {
+            for (int rb = 0; rb < tf::xrow_blocks(d.nx, d.ny); ++rb) { items_xr.push_back(f); items_xr.push_back(rb); }
+        } else {
+            const int txy = (d.ny + tf::TILE - 1) / tf::TILE;
+            for (int ty = 0; ty < txy; ++ty)
+                for (int tx = 0; tx < d.Px; ++tx) { items_x.push_back(f); items_x.push_back(tx); items_x.push_back(ty); }
+            for (int lb = 0; lb < (d.ny + 63) / 64; ++lb) { items_cx.push_back(f); items_cx.push_back(lb); }
+        }
+    }
+    e->ny_items = (int)items_y.size() / 3;
+    e->nx_items = (int)items_x.size() / 3;
+    e->ncy_items = (int)items_cy.size() / 2;
+    e->ncx_items = (int)items_cx.size() / 2;
+    e->nxr_items = (int)items_xr.size() / 2;
+    items.clear();
+    items.insert(items.end(), items_y.begin(), items_y.end());
+    items.insert(items.end(), items_x.begin(), items_x.end());
+    items.insert(items.end(), items_cy.begin(), items_cy.end());
+    items.insert(items.end(), items_cx.begin(), items_cx.end());
+    items.insert(items.end(), items_xr.begin(), items_xr.end());
+}
+
+// Rows of all films: the x sweep of an ensemble is one launch over every film's rows, so the
+// automatic variant choice takes this as its batch.
+int total_rows(const tf_ensemble *e)
+{
+    long long n = 0;
+    for (const auto &d : e->desc) n += d.ny;
+    return (int)std::min(n, (long long)1 << 30);
+}
+
+// Work-list capacity for any choice of x-sweep variants.
+size_t max_items(const tf_ensemble *e)
+{
+    size_t n = 0;
+    for (const auto &d : e->desc) {
+        n += 3 * (size_t)d.Py * ((d.nx + tf::LT0 - 1) / tf::LT0) + 2 * (size_t)((d.nx + 63) / 64);
+        n += std::max(3 * (size_t)((d.ny + tf::TILE - 1) / tf::TILE) * d.Px + 2 * (size_t)((d.ny + 63) / 64),
+                      tf::xrow_supported(d.nx) ? 2 * (size_t)tf::xrow_blocks(d.nx, d.ny) : 0);
+    }
+    return n;
+}
+
 } // namespace
 
 extern "C" {
@@ -154,7 +216,6 @@ tf_status tf_ensemble_create(int nfilms, const int *nx, const int *ny, const dou
     e->S = tf_scheme{1.0, 1e-10, 1e-6, 1.0, 0.5, 1.1, 5000, 5, 0};
     const bool p32 = ((int)n == 3 && (int)m == 2);
     e->km = p32 ? tf::KM_P32 : tf::KM_POWER;
-    std::vector<int> items_y, items_x, items_cy, items_cx;
     for (int f = 0; f < nfilms; ++f) {
         if (nx[f] < 4 || ny[f] < 4 || !(ds[f] > 0.0) || !std::isfinite(kappa[f])) {
             delete e;
@@ -184,30 +245,17 @@ tf_status tf_ensemble_create(int nfilms, const int *nx, const int *ny, const dou
         e->ncells += (long long)nx[f] * ny[f];
         e->nrec += std::max((long long)d.Py * nx[f], (long long)d.Px * ny[f]);
         e->desc.push_back(d);
-        const int tyx = (nx[f] + tf::LT0 - 1) / tf::LT0;
-        for (int ty = 0; ty < d.Py; ++ty)
-            for (int tx = 0; tx < tyx; ++tx) { items_y.push_back(f); items_y.push_back(tx); items_y.push_back(ty); }
-        const int txy = (ny[f] + tf::TILE - 1) / tf::TILE;
-        for (int ty = 0; ty < txy; ++ty)
-            for (int tx = 0; tx < d.Px; ++tx) { items_x.push_back(f); items_x.push_back(tx); items_x.push_back(ty); }
-        for (int lb = 0; lb < (nx[f] + 63) / 64; ++lb) { items_cy.push_back(f); items_cy.push_back(lb); }
-        for (int lb = 0; lb < (ny[f] + 63) / 64; ++lb) { items_cx.push_back(f); items_cx.push_back(lb); }
     }
-    e->ny_items = (int)items_y.size() / 3;
-    e->nx_items = (int)items_x.size() / 3;
-    e->ncy_items = (int)items_cy.size() / 2;
-    e->ncx_items = (int)items_cx.size() / 2;
+    e->xsweep.assign(nfilms, 0);
+    for (int f = 0; f < nfilms; ++f) e->xsweep[f] = tf::xsweep_choice(nx[f], total_rows(e));
     std::vector<int> items;
-    items.insert(items.end(), items_y.begin(), items_y.end());
-    items.insert(items.end(), items_x.begin(), items_x.end());
-    items.insert(items.end(), items_cy.begin(), items_cy.end());
-    items.insert(items.end(), items_cx.begin(), items_cx.end());
+    build_items(e, items);
     const size_t N = (size_t)e->ncells, R = (size_t)e->nrec;
     bool ok = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) == hipSuccess
               && hipMalloc(&e->d_desc, nfilms * sizeof(tf::FilmDesc)) == hipSuccess
               && hipMalloc(&e->d_state, nfilms * sizeof(tf::FilmState)) == hipSuccess
               && hipHostMalloc(&e->h_state, nfilms * sizeof(tf::FilmState), hipHostMallocDefault) == hipSuccess
-              && hipMalloc(&e->d_items, items.size() * sizeof(int)) == hipSuccess
+              && hipMalloc(&e->d_items, max_items(e) * sizeof(int)) == hipSuccess
               && hipMalloc(&e->d_active, sizeof(int)) == hipSuccess
               && hipHostMalloc(&e->h_active, sizeof(int), hipHostMallocDefault) == hipSuccess
               && hipMalloc(&e->buf1, N * sizeof(double)) == hipSuccess
@@ -284,6 +332,31 @@ tf_status tf_ensemble_set_scheme(tf_ensemble *e, const tf_scheme *s)
     e->S = *s;
     drop_graph(e);
     return TF_OK;
+}
+
+tf_status tf_ensemble_set_xsweep(tf_ensemble *e, int variant)
+{
+    if (e == nullptr) return efail(TF_EINVAL, "ensemble is NULL");
+    if (variant != TF_XSWEEP_AUTO && variant != TF_XSWEEP_PARTITIONED && variant != TF_XSWEEP_ROW)
+        return efail(TF_EINVAL, "unknown x-sweep variant");
+    for (int f = 0; f < e->nfilms; ++f) {
+        const tf::FilmDesc &d = e->desc[f];
+        const bool row4 = tf::xrow_supported(d.nx) && d.nx <= tf::XR_ROW4_MAX_NX;
+        e->xsweep[f] = variant == TF_XSWEEP_AUTO ? tf::xsweep_choice(d.nx, total_rows(e))
+                     : (variant == TF_XSWEEP_ROW && row4 ? 1 : 0);
+    }
+    std::vector<int> items;
+    build_items(e, items);
+    TF_EHIP(hipStreamSynchronize(e->stream));
+    TF_EHIP(hipMemcpyAsync(e->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, e->stream));
+    TF_EHIP(hipStreamSynchronize(e->stream));
+    drop_graph(e);
+    return TF_OK;
+}
+
+int tf_ensemble_xsweep(const tf_ensemble *e, int film)
+{
+    return (e == nullptr || film < 0 || film >= e->nfilms) ? -1 : e->xsweep[film];
 }
 
 tf_status tf_ensemble_set_model_linear(tf_ensemble *e, double c0, double c1)

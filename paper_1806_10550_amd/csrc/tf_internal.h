@@ -27,6 +27,16 @@ constexpr int NEXT = 4;                  // doubles per (segment, line) boundary
 constexpr int NCHAIN = 12;               // doubles per (segment, line) chain record
 constexpr int BLOCK = 64 * NSUB;
 
+// Whole-row x sweep (tf_xrow.hip): each lane eliminates XR_CPL consecutive cells of a row;
+// a workgroup of 4 or 8 waves holds one row (of up to XR_MAX_NX cells) or several shorter
+// rows, in xr_lds(waves) doubles of LDS: 4-wave workgroups (rows up to 4096 cells) fit two
+// to a CU, so that one's memory phases overlap the other's arithmetic.
+constexpr int XR_CPL = 16;
+constexpr int XR_WAVES = 8;                          // waves of the largest workgroup
+constexpr int XR_MAX_NX = XR_CPL * 64 * XR_WAVES;
+__host__ __device__ constexpr int xr_lds(int waves) { return waves * 2400; }
+constexpr int XR_ROW4_MAX_NX = XR_CPL * 64 * 4;      // rows a 4-wave workgroup holds
+
 // Segments of a line of n >= 2 cells: TILE cells each, except that a last segment of
 // a single cell borrows one from its neighbour (every segment has >= 2 cells).
 __host__ __device__ inline int seg_count(int n) { return (n + TILE - 1) / TILE; }
@@ -141,6 +151,17 @@ enum ResultFlag { FLAG_NONPOS = 1, FLAG_NAN = 2 };
 hipError_t launch_flux_divergence_f1(int nx, int ny, double ids, double ids2, const Model &M, const double *u,
                                      double *out, hipStream_t s);
 hipError_t launch_pass(int dir, bool solve, const PassParams &p, hipStream_t s);
+// Whole-row x sweep: reads u (u_k) and in2 (w), writes out (u_{k+1}), the reduction record
+// (res: max|v/u_k|, flags) and, when mass is set, one mass record per workgroup.
+bool xrow_supported(int nx);
+int xrow_blocks(int nx, int ny);           // workgroups of one launch (= mass records)
+hipError_t launch_xrow(const PassParams &p, hipStream_t s);
+// x-sweep variant for a film of nx x ny cells (0: partitioned, 1: whole-row): the autotuned
+// choice for the nearest shape, else the built-in rule (tf_adjoint.hip).
+int xsweep_choice(int nx, int ny);
+// Whole-row x sweep over the ensemble's row films (items: (film, row block); every such film
+// has nx <= XR_ROW4_MAX_NX); km: the KernelModel every film shares.
+hipError_t launch_xrow_ens(int km, const EnsParams &e, hipStream_t s);
 hipError_t launch_model_coeffs(const Model &M, const double *h, int n, double *out, hipStream_t s);
 hipError_t launch_chain(const ChainParams &c, hipStream_t s);
 hipError_t launch_flux_divergence(int nx, int ny, double ids, double ids2, const Model &M,

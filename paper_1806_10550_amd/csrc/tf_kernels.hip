@@ -16,7 +16,7 @@
 //                            registers, plug in the segment's outer unknowns and
 //                            back-substitute; write w (y sweep) or u_{k+1} (x sweep).
 // No band matrix is ever stored: coefficients are recomputed from the u tile.
-#include "tf_device.h"
+#include "tf_sweep.h"
 
 namespace tf {
 
@@ -62,20 +62,11 @@ __device__ __forceinline__ double dpp_shift(double v, int ctrl)
 __device__ __forceinline__ double lane_next(double v) { return dpp_shift(v, 0x130); } // wave_shl:1
 __device__ __forceinline__ double lane_prev(double v) { return dpp_shift(v, 0x138); } // wave_shr:1
 
-// Per-cell quantities of the sweeps, scaled so that each face record takes few
-// operations (ka = c / (2 ds^2), c = theta dt):
-//   lap = u_E + u_W + u_N + u_S - 4u      (ds^2 times the 5-point Laplacian)
-//   f0  = cap h^3 / ds^2,   f1 = h^3 Pi'(h)
-//   g0  = ka f0'(h) / ds^2,   g1 = ka f1'(h)
-struct CellS {
-    double u, lap, f0, f1, g0, g1;
-};
-
+// Cell quantities at (line l, position q) of the LDS u tile.
 template <int DIR, int KM>
 __device__ __forceinline__ CellS cell_s(const double *sU, const PassParams &p, int l, int q)
 {
-    CellS c;
-    c.u = uat<DIR>(sU, l, q);
+    const double u = uat<DIR>(sU, l, q);
     double xp, xm, yp, ym;
     if (DIR == 0) {
         xp = uat<DIR>(sU, l + 1, q); xm = uat<DIR>(sU, l - 1, q);
@@ -84,61 +75,7 @@ __device__ __forceinline__ CellS cell_s(const double *sU, const PassParams &p, i
         xp = uat<DIR>(sU, l, q + 1); xm = uat<DIR>(sU, l, q - 1);
         yp = uat<DIR>(sU, l + 1, q); ym = uat<DIR>(sU, l - 1, q);
     }
-    c.lap = __builtin_fma(-4.0, c.u, (xp + xm) + (yp + ym));
-    if constexpr (KM == KM_LINEAR) {
-        c.f0 = p.f0s;
-        c.g0 = 0.0;
-        c.f1 = p.M.Cm;
-        c.g1 = 0.0;
-        return c;
-    }
-    const double r = rcp(c.u);
-    const double u2 = c.u * c.u;
-    c.f0 = (u2 * c.u) * p.f0s;
-    c.g0 = p.K0 * u2;
-    if constexpr (KM == KM_P32) {
-        c.f1 = __builtin_fma(-p.M.Cn, r, p.M.Cm);
-        c.g1 = p.K1 * (r * r);
-    } else if constexpr (KM == KM_POWER) {
-        // r^(m-1), r^(n-1) by fixed-step powering (0 <= m-1 < n-1 <= 15), then one
-        // multiplication by h = 1/r for r^(m-2), r^(n-2)
-        const Model &M = p.M;
-        const double pm1 = pow16(r, M.m - 1), pn1 = pm1 * pow16(r, M.n - M.m);
-        c.f1 = M.Cm * (pm1 * c.u) - M.Cn * (pn1 * c.u);
-        c.g1 = p.ka * (M.Dn * pn1 - M.Dm * pm1);
-    } else {
-        double pip, pipp;
-        if constexpr (KM == KM_NLC) nlc_derivs(p.M, c.u, r, pip, pipp);
-        else polymer_derivs(p.M, c.u, r, pip, pipp);
-        c.f1 = (u2 * c.u) * pip;
-        c.g1 = p.ka * (3.0 * u2 * pip + (u2 * c.u) * pipp);
-    }
-    return c;
-}
-
-// Face record between the cells L and R of a line (raw differences Lam = lap_R - lap_L,
-// Gam = u_R - u_L; A and B are the face means of f0 and f1):
-//   kA = c A / ds^4,
-//   P  = c/ds d(flux)/du_L without the fourth-difference part = ka (f0'_L Lam/ds^2 + f1'_L Gam - 2B),
-//   Q  = the same for u_R with +2B,
-//   F  = 2 ds times the face flux A (lap_R - lap_L)/ds^3 + B Gam/ds  (y sweep only).
-// Boundary faces carry no flux: every entry is zero there.
-struct FaceS {
-    double kA, P, Q, F;
-};
-
-template <bool FLUX>
-__device__ __forceinline__ FaceS face_s(const CellS &L, const CellS &R, bool interior, double ka)
-{
-    const double S0 = L.f0 + R.f0, S1 = L.f1 + R.f1;
-    const double Lam = R.lap - L.lap, Gam = R.u - L.u;
-    const double kS1 = ka * S1;
-    FaceS f;
-    f.kA = interior ? ka * S0 : 0.0;
-    f.P = interior ? __builtin_fma(L.g0, Lam, __builtin_fma(L.g1, Gam, -kS1)) : 0.0;
-    f.Q = interior ? __builtin_fma(R.g0, Lam, __builtin_fma(R.g1, Gam, kS1)) : 0.0;
-    f.F = (FLUX && interior) ? __builtin_fma(S0, Lam, S1 * Gam) : 0.0;
-    return f;
+    return cell_core<KM>(p, u, __builtin_fma(-4.0, u, (xp + xm) + (yp + ym)));
 }
 
 // Elimination sweep of one wave over its sub-segment [ps, ps+len) for all 64 lanes:

@@ -42,6 +42,11 @@ class TFError(RuntimeError):
         self.status = status
 
 
+# x-sweep line-solver variants (include/thinfilm.h, TF_XSWEEP_*)
+XSWEEP = {"auto": -1, "partitioned": 0, "row": 1}
+XSWEEP_NAMES = {0: "partitioned", 1: "row"}
+
+
 _lib = None
 
 
@@ -73,6 +78,9 @@ def lib():
         L.tf_set_scheme.argtypes = [P, C.POINTER(Scheme)]
         L.tf_get_scheme.argtypes = [P, C.POINTER(Scheme)]
         L.tf_set_diagnostics.argtypes = [P, C.c_int]
+        L.tf_set_xsweep.argtypes = [P, C.c_int]
+        L.tf_get_xsweep.argtypes = [P]
+        L.tf_get_xsweep.restype = C.c_int
         L.tf_bind_state.argtypes = [P, P]
         L.tf_step.argtypes = [P, C.POINTER(D), C.POINTER(StepInfo)]
         L.tf_advance.argtypes = [P, C.c_int, C.POINTER(D), P]
@@ -100,6 +108,12 @@ def lib():
         L.tf_autotune_load.argtypes = [C.c_char_p]
         L.tf_autotune_choice.argtypes = [C.c_int, C.c_int, C.c_int]
         L.tf_autotune_choice.restype = C.c_int
+        L.tf_autotune_xsweep.argtypes = [C.c_int, C.c_int, C.c_char_p]
+        L.tf_xsweep_choice.argtypes = [C.c_int, C.c_int]
+        L.tf_xsweep_choice.restype = C.c_int
+        L.tf_ensemble_set_xsweep.argtypes = [P, C.c_int]
+        L.tf_ensemble_xsweep.argtypes = [P, C.c_int]
+        L.tf_ensemble_xsweep.restype = C.c_int
         _lib = L
     return _lib
 
@@ -141,6 +155,7 @@ class Grid:
     """One film of nx x ny cells of side ds; see include/thinfilm.h."""
 
     def __init__(self, nx: int, ny: int, ds: float, stream=None):
+        load_shipped_tuning()  # the x-sweep variant is fixed at creation from the tuning table
         self._h = C.c_void_p()
         _check(lib().tf_create(int(nx), int(ny), float(ds), _stream_ptr(stream), C.byref(self._h)))
         self.nx, self.ny, self.ds = nx, ny, ds
@@ -195,6 +210,14 @@ class Grid:
 
     def set_diagnostics(self, mass_every_step: bool):
         _check(lib().tf_set_diagnostics(self._h, int(bool(mass_every_step))))
+
+    def set_xsweep(self, variant):
+        """x-sweep line solver: "partitioned", "row" or "auto" (tf_set_xsweep)."""
+        code = XSWEEP[variant] if isinstance(variant, str) else int(variant)
+        _check(lib().tf_set_xsweep(self._h, code))
+
+    def xsweep(self) -> str:
+        return XSWEEP_NAMES[lib().tf_get_xsweep(self._h)]
 
     def bind(self, h):
         """Bind a contiguous (ny, nx) float64 CUDA tensor as the state (borrowed)."""
@@ -314,6 +337,7 @@ class Ensemble:
     (include/thinfilm.h, tf_ensemble_*); theta scheme with theta in [0.5, 1]."""
 
     def __init__(self, nx, ny, ds, kappa, b=0.1, n=3, m=2, stream=None):
+        load_shipped_tuning()  # per-film x-sweep variants, as single grids take them
         k = len(nx)
         self.nfilms = k
         self._h = C.c_void_p()
@@ -329,6 +353,14 @@ class Ensemble:
         self.offsets = [int(v) for v in offs]
         self.size = int(lib().tf_ensemble_size(self._h))
         self._state = None
+
+    def set_xsweep(self, variant):
+        """x-sweep line solver of every film: "auto" (each as alone), "row" or "partitioned"."""
+        code = XSWEEP[variant] if isinstance(variant, str) else int(variant)
+        _check(lib().tf_ensemble_set_xsweep(self._h, code))
+
+    def xsweep(self, film: int) -> str:
+        return XSWEEP_NAMES[lib().tf_ensemble_xsweep(self._h, int(film))]
 
     def set_model_linear(self, c0=1.0, c1=1.0):
         _check(lib().tf_ensemble_set_model_linear(self._h, float(c0), float(c1)))
@@ -451,6 +483,18 @@ def autotune(length: int, batch: int, cache_path: str | None = None, transposed:
     _check(lib().tf_autotune(int(length), int(batch), int(bool(transposed)),
                              cache_path.encode() if cache_path else None))
     return VARIANT_NAMES[lib().tf_autotune_choice(int(length), int(batch), int(bool(transposed)))]
+
+
+def autotune_xsweep(length: int, batch: int, cache_path: str | None = None) -> str:
+    """Time the two forward x-sweep variants on a film of `batch` rows of `length` cells
+    (tf_autotune_xsweep); returns the one now chosen for that shape."""
+    _check(lib().tf_autotune_xsweep(int(length), int(batch), cache_path.encode() if cache_path else None))
+    return xsweep_choice(length, batch)
+
+
+def xsweep_choice(nx: int, ny: int) -> str:
+    """x-sweep variant a film of nx x ny cells takes at creation (tf_xsweep_choice)."""
+    return XSWEEP_NAMES[lib().tf_xsweep_choice(int(nx), int(ny))]
 
 
 def autotune_load(cache_path: str) -> None:

@@ -24,6 +24,7 @@ KERNEL_CLASSES = [
     (r"k_pass<1, false", "relations_x"),
     (r"k_pass<1, true", "solve_x"),
     (r"k_chain", "chain"),
+    (r"k_xrow", "xrow"),
     (r"k_mass", "mass"),
     (r"k_flux_divergence", "rhs_theta"),
 ]

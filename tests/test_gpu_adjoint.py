@@ -191,6 +191,33 @@ def test_rollout_gradient_matches_oracle_adjoint(orc):
     assert kap.grad.item() == pytest.approx(gk, rel=1e-8)
 
 
+def test_rollout_on_a_side_stream_matches_default_stream():
+    """A rollout run under another torch stream uses a grid bound to that stream (the grid
+    cache is keyed by stream), so its checkpoint copies and the library's launches stay in
+    order: same h(T) and gradients, bit for bit, as on the default stream."""
+    n, steps, dt = 48, 12, 0.1
+    ds = 16 * synth.lambda_m(10.0) / 512
+    b = gpu(synth.noise_film(n, n, seed=4, amp=0.01))
+    t = gpu(synth.noise_film(n, n, seed=5, amp=0.01))
+
+    def run():
+        p0 = torch.zeros((n, n), dtype=torch.float64, device=DEV, requires_grad=True)
+        kap = torch.tensor(10.0, dtype=torch.float64, device=DEV, requires_grad=True)
+        h = rollout(p0, kap, b, steps, dt, ds, checkpoint_every=4, tol=1e-12, adj_tol=1e-12)
+        _loss(h, t).backward()
+        return h.detach().clone(), p0.grad.clone(), kap.grad.clone()
+
+    ref = run()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        got = run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for a, r in zip(got, ref):
+        assert torch.equal(a, r)
+
+
 def test_full_size_rollout_gradient_matches_finite_differences():
     """The 512^2 adjoint workload as timed (L = 16 lambda_m, 400 backward-Euler steps of dt = 0.1,
     checkpoints every 20, p0 = 0 on the seed-4 film, target = the seed-5 film run forward over the
@@ -305,3 +332,24 @@ def test_adjoint_step_general_power_law_matches_oracle(orc):
     gk, _ = g.adjoint_step(gpu(un), gpu(unp1), dt, lg, tol=1e-14)
     assert np.max(np.abs(lg.cpu().numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
     assert gk == pytest.approx(gk_ref, rel=1e-9)
+
+
+def test_autotune_xsweep_roundtrip(tmp_path):
+    """Forward x-sweep tuning: both variants timed on a 2500-cell row film, the faster one
+    recorded (kind "xsweep") and taken for that shape by new grids; rows above 4096 cells
+    always take the partitioned solver whatever the timing."""
+    from paper_1806_10550_amd.lib import autotune_xsweep, xsweep_choice
+    path = str(tmp_path / "xs.jsonl")
+    choice = autotune_xsweep(2500, 4, path)
+    rec = json.loads(open(path).read().strip().splitlines()[-1])
+    assert rec["kind"] == "xsweep" and rec["length"] == 2500 and rec["batch"] == 4
+    assert set(rec["ms"]) == {"partitioned", "row"} and all(math.isfinite(v) for v in rec["ms"].values())
+    assert rec["variant"] == min(rec["ms"], key=rec["ms"].get) == choice
+    assert xsweep_choice(2500, 4) == choice
+    g = grid(2500, 4, 0.67)
+    assert g.xsweep() == choice
+    g.close()
+    autotune_xsweep(8000, 4, path)
+    assert xsweep_choice(8000, 4) == "partitioned"
+    autotune_load(path)
+    assert xsweep_choice(2500, 4) == choice

@@ -29,10 +29,11 @@ def pack(ens, h0):
     return packed
 
 
-def single(nx, ny, ds, kappa, h0, steps, dt, **scheme):
+def single(nx, ny, ds, kappa, h0, steps, dt, xsweep="auto", **scheme):
     g = Grid(nx, ny, ds)
     g.set_model(kappa, 0.1, 3, 2)
     g.set_scheme(**scheme)
+    g.set_xsweep(xsweep)
     h = torch.from_numpy(h0).to(DEV)
     g.bind(h)
     st, dtn, log = g.try_advance(steps, dt)
@@ -48,7 +49,7 @@ def test_ensemble_equals_single_film_path_bitwise():
     st, dts, sts, its = ens.step(4, 0.1)
     assert st == TF_OK and all(s == TF_OK for s in sts)
     for f in range(len(FILMS)):
-        s1, _, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 4, 0.1, tol=1e-10)
+        s1, _, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 4, 0.1, xsweep=ens.xsweep(f), tol=1e-10)
         assert s1 == TF_OK
         assert torch.equal(ens.view(packed, f), h), f
         assert its[f] == sum(x["total_iters"] for x in log)
@@ -107,7 +108,7 @@ def test_ensemble_adaptive_schedules_match_single_films():
         st, dts, sts, its = ens.step(4, dts)
         assert st == TF_OK
     for f in range(5):
-        s1, dtn, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 12, 0.1, **kw)
+        s1, dtn, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 12, 0.1, xsweep=ens.xsweep(f), **kw)
         assert s1 == TF_OK
         assert dts[f] == dtn
         assert torch.equal(ens.view(packed, f), h), f
@@ -137,6 +138,7 @@ def test_model_ensemble_equals_single_film_path_bitwise(orc, kind, h0s, dt):
     assert st == TF_OK and all(s == TF_OK for s in sts)
     for f in range(len(sizes)):
         g = Grid(nx[f], ny[f], ds[f])
+        g.set_xsweep(ens.xsweep(f))  # the variant the ensemble gives this film
         getattr(g, "set_model_" + kind)()
         g.set_scheme(tol=1e-10)
         h = torch.from_numpy(h0[f]).to(DEV)
@@ -175,7 +177,7 @@ def test_theta_half_ensemble_equals_single_film_path_bitwise(adaptive, dt0):
     assert st == TF_OK and all(s == TF_OK for s in sts)
     rejected = 0
     for f in range(5):
-        s1, dtn, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 6, dt0, **kw)
+        s1, dtn, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 6, dt0, xsweep=ens.xsweep(f), **kw)
         assert s1 == TF_OK
         assert dts[f] == dtn
         assert its[f] == sum(x["total_iters"] for x in log)
@@ -229,6 +231,7 @@ def test_general_power_law_ensemble_equals_single_film_path_bitwise():
     assert st == TF_OK and all(s == TF_OK for s in sts)
     for f in range(len(FILMS)):
         g = Grid(nx[f], ny[f], ds[f])
+        g.set_xsweep(ens.xsweep(f))  # the variant the ensemble gives this film
         g.set_model(kap[f], 0.1, 5, 2)
         g.set_scheme(tol=1e-10)
         h = torch.from_numpy(h0[f]).to(DEV)
@@ -252,7 +255,7 @@ def test_film_info_matches_single_film_log():
     st, _, _, _ = ens.step(5, 0.5)
     assert st == TF_OK
     for f in range(4):
-        s1, _, log, _ = single(nx[f], ny[f], ds[f], kap[f], h0[f], 5, 0.5, **kw)
+        s1, _, log, _ = single(nx[f], ny[f], ds[f], kap[f], h0[f], 5, 0.5, xsweep=ens.xsweep(f), **kw)
         assert s1 == TF_OK
         info = ens.film_info(f)
         last = log[-1]
@@ -287,7 +290,56 @@ def test_random_ragged_ensemble_equals_single_films_bitwise():
     st, dts, sts, its = ens.step(4, 0.2)
     assert st == TF_OK and all(s == TF_OK for s in sts)
     for f in range(len(films)):
-        s1, dtn, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 4, 0.2, **kw)
+        s1, dtn, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 4, 0.2, xsweep=ens.xsweep(f), **kw)
         assert s1 == TF_OK
         assert torch.equal(ens.view(packed, f), h), films[f]
         assert its[f] == sum(x["total_iters"] for x in log) and dts[f] == dtn, films[f]
+
+
+def test_mixed_xsweep_variants_bitwise():
+    """Films whose x sweep takes different variants in one ensemble: rows above 4096 cells take
+    the partitioned solver, shorter rows the whole-row kernel (each as it would alone; the
+    per-film choice is reported by xsweep_choice). The ensemble equals the single-film path bit
+    for bit, adaptive dt."""
+    from paper_1806_10550_amd.lib import xsweep_choice
+    films = [(4200, 12, 10.0), (500, 40, 8.0), (37, 23, 12.0), (3000, 9, 15.0), (64, 130, 6.0)]
+    nx, ny, kap, ds, h0 = films_setup(films)
+    kinds = [xsweep_choice(a, b) for a, b in zip(nx, ny)]
+    assert kinds[0] == "partitioned" and "row" in kinds
+    sch = dict(tol=1e-10, max_newton=10, adaptive=1, dt_min=1e-9, dt_max=1.0, dt_shrink=0.5, dt_grow=1.1,
+               grow_after=5)
+    ens = Ensemble(nx, ny, ds, kap)
+    ens.set_scheme(**sch)
+    packed = pack(ens, h0)
+    ens.bind(packed)
+    st, dts, sts, its = ens.step(3, 0.1)
+    assert st == TF_OK
+    for f in range(len(films)):
+        s1, dtn, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 3, 0.1, xsweep=ens.xsweep(f), **sch)
+        assert s1 == TF_OK
+        assert torch.equal(ens.view(packed, f), h), (f, kinds[f])
+        assert its[f] == sum(x["total_iters"] for x in log)
+        assert dts[f] == dtn
+
+
+@pytest.mark.parametrize("variant", ["row", "partitioned"])
+def test_ensemble_forced_xsweep_bitwise(variant):
+    """tf_ensemble_set_xsweep forces one variant on every film (rows above 4096 cells stay
+    partitioned); each film equals a single film run with the same variant, bit for bit."""
+    films = FILMS + [(4200, 8, 9.0)]
+    nx, ny, kap, ds, h0 = films_setup(films)
+    sch = dict(tol=1e-10, max_newton=10, adaptive=1, dt_min=1e-9, dt_max=1.0, dt_shrink=0.5, dt_grow=1.1,
+               grow_after=5)  # the 4200-cell film (ds ~ 0.04) needs a much smaller dt
+    ens = Ensemble(nx, ny, ds, kap)
+    ens.set_scheme(**sch)
+    ens.set_xsweep(variant)
+    for f in range(len(films)):
+        assert ens.xsweep(f) == (variant if nx[f] <= 4096 else "partitioned")
+    packed = pack(ens, h0)
+    ens.bind(packed)
+    st, dts, sts, its = ens.step(3, 0.1)
+    assert st == TF_OK
+    for f in range(len(films)):
+        s1, _, log, h = single(nx[f], ny[f], ds[f], kap[f], h0[f], 3, 0.1, xsweep=ens.xsweep(f), **sch)
+        assert s1 == TF_OK
+        assert torch.equal(ens.view(packed, f), h), (f, variant)

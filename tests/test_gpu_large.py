@@ -3,7 +3,11 @@
 * 2048^2 spinodal and nucleation films (L = 64 lambda_m, adaptive dt from 0.1 with
   K = 10): the first accepted steps, every cell, dt schedule and rejections.
 * 8192^2 film (L = 256 lambda_m, dt = 0.2): one full Newton iteration, every cell, and
-  the reduction record.
+  the reduction record; the whole first accepted step (every Newton iteration of it)
+  against the oracle's step, every cell.
+* 2048^2 nucleation film near the pre-rupture horizon: from the GPU state at which min h
+  first falls below 0.6, the oracle replays the next 20 accepted steps with the GPU's dt
+  and iteration counts; every cell to 1e-10.
 * 16384^2 film: one Newton iteration (largest size exercised).
 * 2048^2 spinodal over many steps on the GPU alone: mass to 1e-12, positivity.
 """
@@ -67,6 +71,75 @@ def test_8192_newton_iteration_matches_oracle(orc):
     assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(v))
     assert e == pytest.approx(e_ref, rel=1e-9)
     assert r == pytest.approx(r_ref, rel=1e-9)
+
+
+def test_8192_first_accepted_step_matches_oracle(orc):
+    """The whole first step of the 8192^2 workload (fixed dt = 0.2, tol 1e-10) from the noise
+    film: the rough initial noise needs the most Newton iterations of the run. Same
+    iteration count as the oracle's step (Fig. FlowChartTime with a fixed dt) and every cell
+    to 1e-10 relative."""
+    cfg = synth.CONFIGS["large8192"]
+    h0 = cfg.film()
+    g = Grid(cfg.n, cfg.n, cfg.ds)
+    g.set_model(10.0, 0.1, 3, 2)
+    g.set_scheme(theta=1.0, tol=cfg.tol, max_newton=5000, adaptive=0)
+    h = torch.from_numpy(h0).to(DEV)
+    g.bind(h)
+    res = g.step(cfg.dt)
+    got = h.cpu().numpy()
+    del h
+    g.close()
+    torch.cuda.empty_cache()
+    ref, r = orc.step(orc.Model(), orc.Scheme(theta=1.0, tol=cfg.tol, max_newton=5000, adaptive=0), h0, cfg.ds,
+                      cfg.dt)
+    assert r.status == orc.OK and res.info["status"] == 0
+    assert res.info["newton_iters"] == r.newton_iters, (res.info["newton_iters"], r.newton_iters)
+    assert res.info["newton_iters"] >= 6
+    assert np.max(np.abs(got - ref) / ref) <= 1e-10
+
+
+def test_2048_near_horizon_window_matches_oracle_replay(orc):
+    """The 2048^2 nucleation film (Gaussian depression of depth 0.3 over noise, adaptive dt
+    from 0.1 with K = 10) run on the GPU until min h first falls below 0.6, where the
+    depression has deepened by a factor of about 1.5 on its way to rupture. From that state
+    the oracle replays the next 20 accepted steps with the GPU's dt and Newton iteration
+    count per step (A10); h agrees to 1e-10 relative after every 5 steps, and the oracle's
+    own test takes the GPU's accept decision at all but at most two knife edges."""
+    cfg = synth.CONFIGS["nucleation2048"]
+    g = Grid(cfg.n, cfg.n, cfg.ds)
+    g.set_model(10.0, 0.1, 3, 2)
+    g.set_scheme(**ADAPT)
+    g.set_diagnostics(True)
+    h = torch.from_numpy(cfg.film()).to(DEV)
+    g.bind(h)
+    dt, steps = cfg.dt, 0
+    while True:
+        dt, log = g.advance(1, dt, log=True)
+        steps += 1
+        assert steps < 3000
+        if log[0]["hmin"] < 0.6:
+            break
+    start = h.cpu().numpy()
+    logs, snaps = [], {}
+    for _ in range(4):
+        dt, log = g.advance(5, dt, log=True)
+        logs += log
+        snaps[len(logs)] = h.cpu().numpy()
+    g.close()
+    M = orc.Model()
+    u, disagree = start, 0
+    for s, x in enumerate(logs):
+        uk = u
+        for k in range(x["newton_iters"]):
+            uk, e, _ = orc.adi_iteration(M, u, uk, cfg.ds, x["dt_used"], 1.0)
+            if (e < ADAPT["tol"]) != (k == x["newton_iters"] - 1):
+                disagree += 1
+        u = uk
+        if s + 1 in snaps:
+            rel = np.max(np.abs(snaps[s + 1] - u) / u)
+            assert rel <= 1e-10, (steps, s + 1, rel)
+    assert disagree <= 2, disagree
+    assert min(x["hmin"] for x in logs) < 0.6
 
 
 def test_16384_newton_iteration_matches_oracle(orc):

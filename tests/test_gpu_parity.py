@@ -362,3 +362,70 @@ def test_random_shapes_newton_iteration(orc, nx, ny, theta, dt):
         assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref - uk)) + 1e-15, (it, nx, ny)
         assert e == pytest.approx(e_ref, rel=1e-8)
         uk, uk_g = got, out.clone()
+
+
+XSHAPES = [(4, 9), (15, 12), (17, 9), (33, 20), (37, 23), (64, 64), (129, 70), (257, 5), (1000, 7), (2049, 6),
+           (4096, 5), (4097, 4), (8192, 6)]
+
+
+@pytest.mark.parametrize("nx,ny", XSHAPES)
+@pytest.mark.parametrize("variant", ["row", "partitioned"])
+def test_xsweep_variants_match_oracle(orc, nx, ny, variant):
+    """Both x-sweep line solvers (eqs. JacobianSystem2-3), forced on every row length class:
+    rows shorter than one 16-cell sub-segment, lengths 1 above a multiple of 16 (a lone cell
+    in the first sub-segment), one and several waves per row, the 4-wave limit (4096) and
+    the 8-wave rows up to 8192. Two Newton iterates against the oracle (1e-10 of the update)."""
+    ds, dt = 0.67347, 0.2
+    un = synth.noise_film(nx, ny, seed=nx + 7 * ny, amp=0.01)
+    g = make_grid(nx, ny, ds)
+    g.set_xsweep(variant)
+    assert g.xsweep() == variant
+    M = omodel(orc)
+    uk, uk_g, un_g = un, gpu(un), gpu(un)
+    out = torch.empty_like(un_g)
+    for it in range(2):
+        e, r, flags = g.newton_iteration(un_g, uk_g, out, dt)
+        ref, e_ref, r_ref = orc.adi_iteration(M, un, uk, ds, dt, 1.0)
+        got = out.cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref - uk)) + 1e-15, (it, variant)
+        assert flags == 0 and e == pytest.approx(e_ref, rel=1e-8)
+        uk, uk_g = got, out.clone()
+    g.close()
+
+
+def test_xsweep_variants_agree_over_steps():
+    """The two variants reach the same accepted states (the Newton root does not depend on
+    the line solver): 20 adaptive steps of a 200 x 150 film, 1e-12 relative."""
+    h0 = synth.noise_film(200, 150, seed=11, amp=0.05)
+    hs = []
+    for v in ("row", "partitioned"):
+        g = make_grid(200, 150, 0.67347, tol=1e-12, max_newton=10, adaptive=1, dt_min=1e-6, dt_max=1.0,
+                      dt_shrink=0.5, dt_grow=1.1, grow_after=5)
+        g.set_xsweep(v)
+        h = gpu(h0)
+        g.bind(h)
+        g.advance(20, 0.1)
+        hs.append(h.cpu().numpy())
+        g.close()
+    assert np.max(np.abs(hs[0] - hs[1]) / hs[1]) <= 1e-12
+
+
+def test_xsweep_selection():
+    """tf_set_xsweep: the whole-row kernel is refused for rows above 8192 cells; auto takes the
+    creation-time choice (tf_xsweep_choice), which never picks it above 4096 cells."""
+    from paper_1806_10550_amd.lib import xsweep_choice
+    g = make_grid(8200, 4, 0.67)
+    assert g.xsweep() == "partitioned"
+    with pytest.raises(TFError):
+        g.set_xsweep("row")
+    with pytest.raises(TFError):
+        g.set_xsweep(7)
+    g.set_xsweep("auto")
+    assert g.xsweep() == "partitioned"
+    g.close()
+    for n in (64, 256, 1024, 2048, 4097, 8192):
+        g = make_grid(n, 8, 0.67)
+        assert g.xsweep() == xsweep_choice(n, 8)
+        if n > 4096:
+            assert g.xsweep() == "partitioned"
+        g.close()
