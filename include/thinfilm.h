@@ -294,6 +294,23 @@ tf_status tf_spectrum_maxima(const double *q, const double *s, int npoints, doub
  * scratch; synchronises `stream`. TF_EINVAL for bad sizes or variant 2 with n > 2048. */
 tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *rhs, double *x, int transposed,
                          int variant, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): tf_penta_solve with the same arguments
+ * and results, except that it calls no hipMalloc, hipFree or other allocating routine and
+ * does not synchronise: the work is enqueued on `stream` and the call returns. Its scratch
+ * (interface records of the partitioned variant, the factor array of the Thomas variant;
+ * cyclic reduction needs none) is one static device array of TF_NOALLOC_SCRATCH_DOUBLES
+ * doubles (16 MiB) per GPU, held until the process ends. The partitioned variant needs
+ * 36 * ceil(n / 64) * nlines doubles of it, Thomas 3 * n * nlines; a solve that needs more
+ * returns TF_EINVAL (variant -1 first falls back to cyclic reduction for n <= 2048, else to
+ * the partitioned variant). Every call on one GPU shares that GPU's array: calls whose
+ * solves overlap in time on one GPU (other streams or threads) race and give wrong
+ * results; calls on one stream are ordered and safe. The array needs no clearing (each
+ * solve writes the scratch it reads). TF_EDEVICE if the array's device address cannot be
+ * obtained. */
+#define TF_NOALLOC_SCRATCH_DOUBLES (1 << 21)
+tf_status tf_penta_solve_noalloc(int nlines, int n, const double *bands, const double *rhs, double *x,
+                                 int transposed, int variant, void *stream);
 /* Time the candidates -- partitioned; Thomas with 64, 128 and 256 lines per workgroup;
  * block cyclic reduction (length <= 2048) -- on random diagonally dominant systems of
  * the given length and batch, plain (transposed = 0) or transposed solves (median of 5

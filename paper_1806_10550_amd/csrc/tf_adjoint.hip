@@ -868,6 +868,46 @@ void release_adjoint(const tf_grid *g)
 }
 } // namespace tf_detail
 
+// ---- scratch of the entry point that allocates nothing --------------------------------
+// tf_penta_solve_noalloc takes the interface records (partitioned variant) or the factor
+// work array (Thomas variant) from this array instead of hipMalloc. Each GPU the library
+// runs on holds its own copy until the process ends; host code reaches it only through the
+// device address hipGetSymbolAddress returns (the symbol itself is a host-side stand-in).
+static __device__ __align__(256) double scratch[TF_NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+double *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {}; // device address of `scratch`, per device
+
+// Device address of the scratch array on the current device (looked up once per device).
+tf_status noalloc_scratch(double **out)
+{
+    int dev = 0;
+    TF_AHIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return afail(TF_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[dev] == nullptr) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            return afail(TF_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_noalloc_ptr[dev] = (double *)ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return TF_OK;
+}
+
+// Scratch doubles a solve of nlines lines of n cells needs with a variant.
+size_t scratch_need(int variant, int n, int nlines)
+{
+    const size_t recs = (size_t)tf::seg_count(n) * nlines;
+    if (variant == V_PARTITIONED) return recs * (tf::NREL + tf::NEXT + tf::NCHAIN);
+    if (variant == V_THOMAS) return 3 * (size_t)n * nlines;
+    return 0; // cyclic reduction works in LDS
+}
+} // namespace
+
 extern "C" {
 
 tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, double dt, double *lambda_inout,
@@ -1006,6 +1046,39 @@ tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *r
     (void)hipFree(S.chain);
     (void)hipFree(S.work);
     return st;
+}
+
+tf_status tf_penta_solve_noalloc(int nlines, int n, const double *bands, const double *rhs, double *x,
+                                 int transposed, int variant, void *stream)
+{
+    if (nlines < 1 || n < 2 || bands == nullptr || rhs == nullptr || x == nullptr || variant < -1 || variant > 2)
+        return afail(TF_EINVAL, "bad argument");
+    if (variant == V_PCR && n > tf::PCR_MAX) return afail(TF_EINVAL, "cyclic reduction needs n <= 2048");
+    Choice c;
+    if (variant < 0) {
+        c = pick_variant(n, nlines, transposed != 0);
+        // an automatic choice that does not fit the scratch array falls back to one that does
+        if (scratch_need(c.variant, n, nlines) > (size_t)TF_NOALLOC_SCRATCH_DOUBLES) {
+            if (n <= tf::PCR_MAX) c.variant = V_PCR;
+            else c.variant = V_PARTITIONED;
+        }
+    } else {
+        c.variant = variant;
+    }
+    const size_t need = scratch_need(c.variant, n, nlines);
+    if (need > (size_t)TF_NOALLOC_SCRATCH_DOUBLES)
+        return afail(TF_EINVAL, "the solve needs " + std::to_string(need) + " doubles of scratch; the no-allocation "
+                                "entry point holds " + std::to_string((size_t)TF_NOALLOC_SCRATCH_DOUBLES));
+    double *base = nullptr;
+    tf_status st = noalloc_scratch(&base);
+    if (st != TF_OK) return st;
+    const size_t recs = (size_t)tf::seg_count(n) * nlines;
+    Scratch S;
+    S.rel = base;
+    S.ext = base + recs * tf::NREL;
+    S.chain = base + recs * (tf::NREL + tf::NEXT);
+    S.work = base;
+    return sb_solve(c, transposed != 0, 0, nlines, n, bands, rhs, x, nullptr, S, (hipStream_t)stream);
 }
 
 tf_status tf_autotune(int length, int batch, int transposed, const char *cache_path)

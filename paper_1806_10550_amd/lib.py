@@ -104,6 +104,7 @@ def lib():
         L.tf_adjoint_step.argtypes = [P, P, P, D, P, DP, D, C.c_int, IP]
         L.tf_jacobian_apply_t.argtypes = [P, P, P, P]
         L.tf_penta_solve.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, C.c_int, P]
+        L.tf_penta_solve_noalloc.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, C.c_int, P]
         L.tf_autotune.argtypes = [C.c_int, C.c_int, C.c_int, C.c_char_p]
         L.tf_autotune_load.argtypes = [C.c_char_p]
         L.tf_autotune_choice.argtypes = [C.c_int, C.c_int, C.c_int]
@@ -432,6 +433,17 @@ def penta_solve(bands, rhs, x, transposed=False, variant="auto", stream=None):
         raise ValueError("bands must be (5, n, nlines) and rhs, x (n, nlines)")
     _check(lib().tf_penta_solve(int(nl), int(n), _ptr(bands), _ptr(rhs), _ptr(x), int(bool(transposed)),
                                 VARIANTS[variant], _stream_ptr(stream)))
+    return x
+
+
+def penta_solve_noalloc(bands, rhs, x, transposed=False, variant="auto", stream=None):
+    """tf_penta_solve_noalloc: the same solve with the library's static scratch array (no
+    device allocation, no synchronisation: the work is enqueued on the stream)."""
+    n, nl = rhs.shape
+    if tuple(bands.shape) != (5, n, nl) or tuple(x.shape) != (n, nl):
+        raise ValueError("bands must be (5, n, nlines) and rhs, x (n, nlines)")
+    _check(lib().tf_penta_solve_noalloc(int(nl), int(n), _ptr(bands), _ptr(rhs), _ptr(x), int(bool(transposed)),
+                                        VARIANTS[variant], _stream_ptr(stream)))
     return x
 
 

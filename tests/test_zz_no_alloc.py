@@ -1,0 +1,78 @@
+"""tf_penta_solve_noalloc (the entry point for callers that cannot allocate device memory)
+against tf_penta_solve through the C ABI: same kernels, so the same bits, on two calls in a
+row (the second smaller, reusing the static scratch array), for every variant and both
+orientations; sizes beyond the scratch array are refused on the host."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1806_10550_amd.lib import TFError, penta_solve, penta_solve_noalloc
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+MAX_DOUBLES = 1 << 21  # TF_NOALLOC_SCRATCH_DOUBLES
+
+
+def _bands(n, nl, seed):
+    rng = np.random.default_rng(seed)
+    b = rng.standard_normal((5, n, nl))
+    b[2] = 6.0 + rng.random((n, nl))
+    for p in range(n):
+        for o in range(5):
+            if not 0 <= p + o - 2 < n:
+                b[o, p, :] = 0.0
+    return torch.from_numpy(b).to(DEV)
+
+
+def _case(n, nl, seed):
+    rng = np.random.default_rng(seed + 1)
+    return _bands(n, nl, seed), torch.from_numpy(rng.standard_normal((n, nl))).to(DEV)
+
+
+@pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr", "auto"])
+@pytest.mark.parametrize("transposed", [False, True])
+def test_noalloc_equals_penta_solve_twice(variant, transposed):
+    for (n, nl), seed in (((1000, 300), 3), ((130, 70), 4)):   # second call smaller
+        bands, rhs = _case(n, nl, seed)
+        ref = torch.empty_like(rhs)
+        penta_solve(bands, rhs, ref, transposed=transposed, variant=variant)
+        got = torch.full_like(rhs, float("nan"))
+        penta_solve_noalloc(bands, rhs, got, transposed=transposed, variant=variant)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), (variant, transposed, n, nl)
+        # the solution satisfies the system (rows p - 2 .. p + 2 of each line)
+        b, x, r = bands.cpu().numpy(), got.cpu().numpy(), rhs.cpu().numpy()
+        res = np.zeros_like(r)
+        for o in range(5):
+            sh = o - 2
+            lo, hi = max(0, -sh), min(n, n - sh)
+            if not transposed:
+                res[lo:hi] += b[o, lo:hi] * x[lo + sh:hi + sh]
+            else:
+                # (A^T x)_p = sum_o A[p - sh, p] x[p - sh] with A[q, q + sh] = b[o, q]
+                res[lo + sh:hi + sh] += b[o, lo:hi] * x[lo:hi]
+        assert np.max(np.abs(res - r)) <= 1e-10 * np.max(np.abs(r))
+
+
+def test_noalloc_rejects_solves_beyond_its_scratch():
+    # partitioned: 36 doubles per (64-cell segment, line); Thomas: 3 per cell
+    n, nl = 8192, 1000
+    assert 36 * (n // 64) * nl > MAX_DOUBLES
+    bands = torch.zeros((5, n, nl), dtype=torch.float64, device=DEV)
+    bands[2] = 1.0
+    rhs = torch.ones((n, nl), dtype=torch.float64, device=DEV)
+    x = torch.empty_like(rhs)
+    with pytest.raises(TFError, match="scratch"):
+        penta_solve_noalloc(bands, rhs, x, variant="partitioned")
+    n2, nl2 = 2048, 400
+    assert 3 * n2 * nl2 > MAX_DOUBLES
+    b2 = torch.zeros((5, n2, nl2), dtype=torch.float64, device=DEV)
+    b2[2] = 2.0
+    r2 = torch.ones((n2, nl2), dtype=torch.float64, device=DEV)
+    x2 = torch.empty_like(r2)
+    with pytest.raises(TFError, match="scratch"):
+        penta_solve_noalloc(b2, r2, x2, variant="thomas")
+    # the automatic choice falls back to a variant that fits (cyclic reduction, n <= 2048)
+    penta_solve_noalloc(b2, r2, x2, variant="auto")
+    torch.cuda.synchronize()
+    assert torch.allclose(x2, torch.full_like(x2, 0.5), rtol=0, atol=1e-15)
