@@ -36,7 +36,8 @@ ALGO_BYTES_PER_CELL = {"relations_y": 16, "solve_y": 24, "relations_x": 16, "sol
 KERNEL_SOURCES = ["paper_1806_10550_amd/csrc/tf_kernels.hip", "paper_1806_10550_amd/csrc/tf_internal.h",
                   "paper_1806_10550_amd/csrc/tf_device.h", "paper_1806_10550_amd/csrc/tf_sweep.h",
                   "paper_1806_10550_amd/csrc/tf_xrow.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large8192.json")
+def traffic_file(config="large8192"):
+    return os.path.join(ROOT, "profiles", f"traffic_{config}.json")
 
 
 def kernel_hash():
@@ -47,14 +48,15 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-SQ_FILE = os.path.join(ROOT, "profiles", "sq_large8192.json")
+def sq_file(config="large8192"):
+    return os.path.join(ROOT, "profiles", f"sq_{config}.json")
 
 
-def fp64_flops_for(kernel):
+def fp64_flops_for(kernel, config="large8192"):
     """FP64 flops per launch of a kernel class from the committed SQ counter summary, or None
     when absent or taken on different kernel sources."""
     try:
-        with open(SQ_FILE) as f:
+        with open(sq_file(config)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -68,17 +70,17 @@ def fp64_flops_for(kernel):
 def copy_rate_gbs():
     """The plain copy's measured rate from the committed counter summary (any kernel sources)."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file()) as f:
             return json.load(f).get("copy_gbs")
     except (OSError, ValueError):
         return None
 
 
-def iteration_traffic(ncells):
-    """HBM bytes of one Newton iteration (the six sweep launches) from the committed counter
-    summary, or None when absent or taken on different kernel sources."""
+def iteration_traffic(ncells, config="large8192"):
+    """HBM bytes of one Newton iteration (the sweep launches) from the committed counter
+    summary of the workload, or None when absent or taken on different kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(config)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -93,11 +95,11 @@ def iteration_traffic(ncells):
                for k, n in per.items())
 
 
-def traffic_for(kernel, ncells):
+def traffic_for(kernel, ncells, config="large8192"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None when
     absent or taken on different kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(config)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -107,20 +109,29 @@ def traffic_for(kernel, ncells):
     return (k["fetch_kib"] + k["write_kib"]) * 1024.0 * t.get("copy_scale", 1.0)
 
 
-def cpu_baseline(h_np, ds, dt, scheme, successes, model="power"):
-    """The oracle (plain C, OpenMP over independent lines) timed on the host cores for ONE
-    full accepted step (every Newton iteration of it) of the same film from the state the
-    GPU run ended at, with the same scheme: steps/s = 1 / t_step. Also per Newton iteration
-    (the unit that does not depend on the step window) and one thread on a 1/64 sub-film."""
+def cpu_baseline(h_np, ds, dt, scheme, successes, model="power", max_steps=1, budget_s=10.0):
+    """The oracle (plain C, OpenMP over independent lines) timed on the host cores for whole
+    accepted steps (every Newton iteration of each) of the same film from the state the GPU
+    run ended at, with the same scheme: consecutive steps until `budget_s` seconds have been
+    spent or `max_steps` steps taken (at least one), steps/s = steps / time. Also per Newton
+    iteration (the unit that does not depend on the step window) and one thread on a 1/64
+    sub-film."""
     from oracle import oracle as orc
     threads = len(os.sched_getaffinity(0))
     orc.set_threads(threads)
     M = orc.Model(kappa=10.0, b=0.1, n=3.0, m=2.0) if model == "power" else getattr(orc.Model, model)()
     S = orc.Scheme(**scheme)
+    u, steps, iters, status = h_np, 0, 0, 0
     t0 = time.perf_counter()
-    _, res = orc.step(M, S, h_np, ds, dt, successes)
-    t_step = time.perf_counter() - t0
-    iters = res.total_iters
+    while True:
+        u, res = orc.step(M, S, u, ds, dt, successes)
+        steps += 1
+        iters += res.total_iters
+        status = res.status
+        dt, successes = res.dt_next, res.successes
+        t_all = time.perf_counter() - t0
+        if res.status != 0 or steps >= max_steps or t_all >= budget_s:
+            break
     cores = orc.get_threads()
     # one thread: one Newton iteration on the top-left eighth by eighth of the film, scaled
     # by the cell count
@@ -130,12 +141,13 @@ def cpu_baseline(h_np, ds, dt, scheme, successes, model="power"):
     orc.adi_iteration(M, sub, sub, ds, dt, scheme.get("theta", 1.0))
     t_1 = (time.perf_counter() - t0) * (h_np.size / sub.size)
     orc.set_threads(threads)
-    return {"value": 1.0 / t_step, "unit": "steps/s", "cores": cores, "kind": "oracle",
-            "sample": (f"one accepted step of the {h_np.shape[1]}x{h_np.shape[0]} film from the state the GPU "
-                       f"run ended at ({iters} Newton iterations, {t_step:.2f} s, status {res.status})"),
+    return {"value": steps / t_all, "unit": "steps/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{steps} consecutive accepted step(s) of the {h_np.shape[1]}x{h_np.shape[0]} film from the "
+                       f"state the GPU run ended at ({iters} Newton iterations, {t_all:.2f} s, last status {status})"),
+            "steps": steps,
             "newton_iters": iters,
-            "ms_per_newton_iteration": 1e3 * t_step / max(iters, 1),
-            "grid_point_iterations_per_s": h_np.size * iters / t_step,
+            "ms_per_newton_iteration": 1e3 * t_all / max(iters, 1),
+            "grid_point_iterations_per_s": h_np.size * iters / t_all,
             "single_thread_ms_per_newton_iteration": 1e3 * t_1,
             "single_thread_sample": (f"one Newton iteration on {sub.shape[1]}x{sub.shape[0]} cells of the same "
                                      f"film on one thread, scaled to the full film")}
@@ -460,7 +472,7 @@ def main():
         ["xrow"] if prof.get("xrow", (0, 0))[1] else ["relations_x", "chain_x", "solve_x"])
     iter_kernel_s = sum(prof[k][0] for k in sweep) / 1e3 / total_iters
     achieved = ALGO_BYTES_PER_CELL_ITERATION * ncells / iter_kernel_s / 1e9
-    traffic = iteration_traffic(ncells) if args.model == "power" else None
+    traffic = iteration_traffic(ncells, args.config) if args.model == "power" else None
     kernel_ms = sum(v[0] for v in prof.values())
     iter_frac = (ALGO_BYTES_PER_CELL_ITERATION * ncells * total_iters) / (elapsed * HBM_PEAK_GBS * 1e9)
     dom = max((k for k in ALGO_BYTES_PER_CELL if k in prof), key=lambda k: prof[k][0])
@@ -503,12 +515,14 @@ def main():
         # bytes per launch) and its FP64 rate from the committed SQ counters
         "dominant_kernel": {"kernel": dom, "mean_us": 1e6 * dom_s,
                             "algorithmic_gbs": ALGO_BYTES_PER_CELL[dom] * ncells / dom_s / 1e9,
-                            "traffic": traffic_for(dom, ncells) if args.model == "power" else None,
-                            "fp64_tflops": (fp64_flops_for(dom) / dom_s / 1e12) if fp64_flops_for(dom) else None},
+                            "traffic": traffic_for(dom, ncells, args.config) if args.model == "power" else None,
+                            "fp64_tflops": ((fp64_flops_for(dom, args.config) / dom_s / 1e12)
+                                            if fp64_flops_for(dom, args.config) else None)},
     }
     if not args.no_cpu_baseline:
         h_now = h.cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(h_now, ds, dt_end, scheme, g.clock()[1], args.model)
+        out["cpu_baseline"] = cpu_baseline(h_now, ds, dt_end, scheme, g.clock()[1], args.model,
+                                           max_steps=args.steps)
     print(json.dumps(out), flush=True)
     g.close()
 

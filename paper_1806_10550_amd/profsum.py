@@ -3,10 +3,10 @@
   python -m paper_1806_10550_amd.profsum stats DIR [--title T]
       kernel-trace statistics (DIR holds *kernel_stats.csv) as a text table
   python -m paper_1806_10550_amd.profsum traffic --fetch D1 --write D2 --copy-fetch D3 \
-      --copy-write D4 --copy-bytes B --hash H
+      --copy-write D4 --copy-bytes B --hash H [--bench-args ARGS]
       per-kernel FETCH_SIZE / WRITE_SIZE per dispatch (KiB), with the scale factor that
       maps the counters onto the known byte count of a plain copy kernel, as JSON
-  python -m paper_1806_10550_amd.profsum sq DIR [DIR ...] --hash H
+  python -m paper_1806_10550_amd.profsum sq DIR [DIR ...] --hash H [--bench-args ARGS]
       per-kernel means per dispatch of the SQ counters of the given runs, as JSON
 """
 import argparse
@@ -85,21 +85,26 @@ def copy_duration_us(d, counter):
     return statistics.mean(durs) if durs else None
 
 
-# the counter runs this record summarises (R: the repository root, OUT: any output
-# directory; run from /tmp with TMPDIR=/tmp); one counter per pass
-COMMANDS = [
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_fetch -o run -- "
-    "python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_write -o run -- "
-    "python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/copy_fetch -o run -- "
-    "python $R/bench.py --calibrate-copy",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/copy_write -o run -- "
-    "python $R/bench.py --calibrate-copy",
-    "python -m paper_1806_10550_amd.profsum traffic --fetch $OUT/pmc_fetch --write $OUT/pmc_write "
-    "--copy-fetch $OUT/copy_fetch --copy-write $OUT/copy_write --copy-bytes 1073741824 "
-    "--hash $(python bench.py --print-hash)",
-]
+# kernel classes that make up one iteration of the ADI-Newton step (the ones the records keep)
+STEP_CLASSES = ("relations_y", "solve_y", "relations_x", "solve_x", "chain", "xrow")
+
+
+def commands(bench_args):
+    """The counter runs a traffic record summarises (R: the repository root, OUT: any output
+    directory; run from /tmp with TMPDIR=/tmp); one counter per pass. bench_args: the
+    arguments of the profiled bench.py run."""
+    run = f"python $R/bench.py {bench_args}"
+    return [
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_fetch -o run -- {run}",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_write -o run -- {run}",
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/copy_fetch -o run -- "
+        "python $R/bench.py --calibrate-copy",
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/copy_write -o run -- "
+        "python $R/bench.py --calibrate-copy",
+        "python -m paper_1806_10550_amd.profsum traffic --fetch $OUT/pmc_fetch --write $OUT/pmc_write "
+        "--copy-fetch $OUT/copy_fetch --copy-write $OUT/copy_write --copy-bytes 1073741824 "
+        f"--bench-args '{bench_args}' --hash $(python bench.py --print-hash)",
+    ]
 
 
 def traffic(a):
@@ -112,7 +117,7 @@ def traffic(a):
     cw_kib = max(cw.values())
     known_kib = a.copy_bytes / 1024.0
     out = {
-        "commands": COMMANDS,
+        "commands": commands(a.bench_args),
         "kernel_hash": a.hash,
         "copy_bytes": a.copy_bytes,
         "copy_fetch_kib": cf_kib,
@@ -126,7 +131,7 @@ def traffic(a):
     }
     for name in fetch:
         cls = classify(name)
-        if cls not in ("relations_y", "solve_y", "relations_x", "solve_x", "chain"):
+        if cls not in STEP_CLASSES:
             continue
         rec = out["kernels"].setdefault(cls, {"fetch_kib": 0.0, "write_kib": 0.0, "dispatches": 0})
         rec["fetch_kib"] = fetch[name] * (known_kib / cf_kib)
@@ -139,26 +144,29 @@ def traffic(a):
     return out
 
 
-SQ_COMMANDS = [
-    "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 "
-    "SQ_INSTS_VALU_ADD_F64 SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES --output-format csv -d $OUT/pmc_sqa -o run -- "
-    "python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-    "rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_WAIT_INST_ANY SQ_INSTS_LDS SQ_ACTIVE_INST_LDS SQ_INSTS_SALU "
-    "--output-format csv -d $OUT/pmc_sqb -o run -- python $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-    "python -m paper_1806_10550_amd.profsum sq $OUT/pmc_sqa $OUT/pmc_sqb --hash $(python bench.py --print-hash)",
-]
+def sq_commands(bench_args):
+    run = f"python $R/bench.py {bench_args}"
+    return [
+        "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU_FMA_F64 "
+        "SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64 SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES "
+        f"--output-format csv -d $OUT/pmc_sqa -o run -- {run}",
+        "rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_WAIT_INST_ANY SQ_INSTS_LDS SQ_ACTIVE_INST_LDS "
+        f"SQ_INSTS_SALU --output-format csv -d $OUT/pmc_sqb -o run -- {run}",
+        f"python -m paper_1806_10550_amd.profsum sq $OUT/pmc_sqa $OUT/pmc_sqb --bench-args '{bench_args}' "
+        "--hash $(python bench.py --print-hash)",
+    ]
 
 
-def sq(dirs, khash):
+def sq(dirs, khash, bench_args):
     """Per kernel class: the mean per dispatch of every SQ counter in the given runs (counters
     summed over the device's shader engines by rocprofv3)."""
-    out = {"commands": SQ_COMMANDS, "kernel_hash": khash, "kernels": {}}
+    out = {"commands": sq_commands(bench_args), "kernel_hash": khash, "kernels": {}}
     for d in dirs:
         path = _find(d, "*counter_collection.csv")
         acc = {}
         for r in csv.DictReader(open(path)):
             cls = classify(r.get("Kernel_Name", ""))
-            if cls not in ("relations_y", "solve_y", "relations_x", "solve_x", "chain"):
+            if cls not in STEP_CLASSES:
                 continue
             acc.setdefault(cls, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
         for cls, cs in acc.items():
@@ -179,14 +187,16 @@ def main():
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--hash", required=True)
+    t.add_argument("--bench-args", default="--steps 2 --warmup 1 --no-cpu-baseline")
     q = sub.add_parser("sq")
     q.add_argument("dirs", nargs="+")
     q.add_argument("--hash", required=True)
+    q.add_argument("--bench-args", default="--steps 2 --warmup 1 --no-cpu-baseline")
     a = ap.parse_args()
     if a.cmd == "stats":
         print(stats(a.dir, a.title))
     elif a.cmd == "sq":
-        print(json.dumps(sq(a.dirs, a.hash), indent=1))
+        print(json.dumps(sq(a.dirs, a.hash, a.bench_args), indent=1))
     else:
         print(json.dumps(traffic(a), indent=1))
 

@@ -6,6 +6,8 @@ import re
 import subprocess
 import sys
 
+import pytest
+
 import bench
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -51,24 +53,31 @@ def test_committed_profiles_carry_a_kernel_hash_and_stale_ones_are_not_used():
         assert bench.fp64_flops_for("solve_x") is None
 
 
-def test_counter_summaries_are_usable():
-    """Every tile kernel class has fetch and write bytes per dispatch, and the dominant kernel has
-    an FP64 flop count (the counter is per wave instruction: 64 lanes each)."""
-    with open(bench.TRAFFIC_FILE) as f:
+@pytest.mark.parametrize("config,n", [("large8192", 8192), ("spinodal2048", 2048)])
+def test_counter_summaries_are_usable(config, n):
+    """Every sweep kernel class of the workload has fetch and write bytes per dispatch (never
+    below its algorithmic bytes), the whole iteration at least 48 B per cell, and the dominant
+    kernel of the 8192^2 workload an FP64 flop count (per wave instruction: 64 lanes each)."""
+    path = bench.traffic_file(config)
+    if not os.path.exists(path):
+        pytest.skip(f"no counter summary for {config}")
+    with open(path) as f:
         t = json.load(f)
     if t["kernel_hash"] != bench.kernel_hash():
         return  # a stale summary is never used (previous test)
-    for k in bench.ALGO_BYTES_PER_CELL:
+    present = [k for k in bench.ALGO_BYTES_PER_CELL if k in t["kernels"]]
+    assert {"relations_y", "solve_y"} <= set(present)
+    for k in present:
         rec = t["kernels"][k]
         assert rec["fetch_kib"] > 0 and rec["write_kib"] > 0 and rec["dispatches"] > 0
-        # counter traffic is never below the algorithmic bytes of an 8192^2 launch
-        algo_kib = bench.ALGO_BYTES_PER_CELL[k] * 8192 * 8192 / 1024
+        algo_kib = bench.ALGO_BYTES_PER_CELL[k] * n * n / 1024
         assert rec["fetch_kib"] + rec["write_kib"] >= algo_kib, k
-    assert bench.iteration_traffic(8192 * 8192) >= 48 * 8192 * 8192
-    with open(bench.SQ_FILE) as f:
-        if json.load(f)["kernel_hash"] == bench.kernel_hash():
-            flops = bench.fp64_flops_for("solve_x")
-            assert flops is not None and flops > 100 * 8192 * 8192
+    assert bench.iteration_traffic(n * n, config) >= 48 * n * n
+    if config == "large8192" and os.path.exists(bench.sq_file(config)):
+        with open(bench.sq_file(config)) as f:
+            if json.load(f)["kernel_hash"] == bench.kernel_hash():
+                flops = bench.fp64_flops_for("solve_x")
+                assert flops is not None and flops > 100 * 8192 * 8192
 
 
 def test_step_count_must_be_positive():
