@@ -251,6 +251,11 @@ def bench_adjoint(args):
     g = Grid(n, n, cfg.ds)
     g.set_model(cfg.kappa, cfg.b, 3, 2)
     g.set_scheme(theta=1.0, tol=cfg.tol, max_newton=5000)
+    if args.xsweep != "auto":
+        # the x-sweep variant of the forward and of the adjoint's transposed row solves
+        from paper_1806_10550_amd import adjoint
+        g.set_xsweep(args.xsweep)
+        adjoint._grid(n, n, cfg.ds).set_xsweep(args.xsweep)
     g.bind(tgt)
     g.advance(steps, dt)                      # target = forward run from seed 5
     h = base.clone()
@@ -289,7 +294,7 @@ def bench_adjoint(args):
                                   f"loss 0.5||h(T)-h_target||^2"},
            "forward_s": t_fwd, "forward_plus_adjoint_s": t_adj, "forward_newton_iters": fwd_iters,
            "richardson_iters": Rollout.stats["richardson_iters"],
-           "solver_variant": autotune_choice(n, n, transposed=True),
+           "solver_variant": autotune_choice(n, n, transposed=True), "xsweep": g.xsweep(),
            "loss": loss.item(), "grad_p0_norm": p0.grad.norm().item(), "grad_kappa": kap.grad.item()}
     print(json.dumps(out), flush=True)
 
@@ -351,7 +356,7 @@ def main():
                          "spectrum: radial Fourier transform of a 4000^2 film")
     ap.add_argument("--films", type=int, default=256)
     ap.add_argument("--xsweep", default="auto", choices=["auto", "row", "partitioned"],
-                    help="ensemble workload: x-sweep line solver of the films (auto: each as alone)")
+                    help="ensemble and adjoint workloads: x-sweep line solver (auto: as tuned for the shape)")
     ap.add_argument("--model", default="power", choices=["power", "nlc", "polymer"],
                     help="single workload only: the power law of the default workload, or the NLC "
                          "(H0 = 0.5) / polymer (H0 = 3.9) film on the same grid with L = 256 lambda_m "

@@ -132,7 +132,9 @@ tf_status tf_set_diagnostics(tf_grid *g, int mass_every_step);
  *                          LDS (4 <= nx <= 8192);
  *   TF_XSWEEP_AUTO         the row kernel when nx allows it (the default at tf_create).
  * TF_EINVAL for an unknown variant or TF_XSWEEP_ROW with nx > 8192. tf_get_xsweep returns
- * the variant in use (-1 for a NULL grid). */
+ * the variant in use (-1 for a NULL grid). The transposed row solves of tf_adjoint_step
+ * follow the setting: TF_XSWEEP_ROW (with nx <= 4096) solves whole rows in one kernel,
+ * otherwise the tuned stored-band solver (tf_autotune) other than that kernel is used. */
 #define TF_XSWEEP_AUTO (-1)
 #define TF_XSWEEP_PARTITIONED 0
 #define TF_XSWEEP_ROW 1
@@ -289,9 +291,11 @@ tf_status tf_spectrum_maxima(const double *q, const double *s, int npoints, doub
  * coefficients a..e at (p, l); entries reaching outside the line must be zero).
  * transposed != 0 solves with the transposed matrices. variant: 0 = partitioned
  * (64-cell segments, interface chain), 1 = one lane per line (Thomas), 2 = block cyclic
- * reduction in LDS (one workgroup per line, n <= 2048), -1 = the autotuned choice. No
- * pivoting: the matrices must be factorable without it. Allocates and frees its own
- * scratch; synchronises `stream`. TF_EINVAL for bad sizes or variant 2 with n > 2048. */
+ * reduction in LDS (one workgroup per line, n <= 2048), 3 = whole lines in one kernel
+ * (16-cell sub-segments per lane coupled by a tree of merges in LDS, 4 <= n <= 4096),
+ * -1 = the autotuned choice. No pivoting: the matrices must be factorable without it.
+ * Allocates and frees its own scratch; synchronises `stream`. TF_EINVAL for bad sizes,
+ * variant 2 with n > 2048 or variant 3 with n outside 4..4096. */
 tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *rhs, double *x, int transposed,
                          int variant, void *stream);
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
@@ -299,7 +303,7 @@ tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *r
  * and results, except that it calls no hipMalloc, hipFree or other allocating routine and
  * does not synchronise: the work is enqueued on `stream` and the call returns. Its scratch
  * (interface records of the partitioned variant, the factor array of the Thomas variant;
- * cyclic reduction needs none) is one static device array of TF_NOALLOC_SCRATCH_DOUBLES
+ * cyclic reduction and the whole-line variant need none) is one static device array of TF_NOALLOC_SCRATCH_DOUBLES
  * doubles (16 MiB) per GPU, held until the process ends. The partitioned variant needs
  * 36 * ceil(n / 64) * nlines doubles of it, Thomas 3 * n * nlines; a solve that needs more
  * returns TF_EINVAL (variant -1 first falls back to cyclic reduction for n <= 2048, else to
@@ -312,14 +316,15 @@ tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *r
 tf_status tf_penta_solve_noalloc(int nlines, int n, const double *bands, const double *rhs, double *x,
                                  int transposed, int variant, void *stream);
 /* Time the candidates -- partitioned; Thomas with 64, 128 and 256 lines per workgroup;
- * block cyclic reduction (length <= 2048) -- on random diagonally dominant systems of
+ * block cyclic reduction (length <= 2048); whole lines in one kernel (4 <= length <= 4096)
+ * -- on random diagonally dominant systems of
  * the given length and batch, plain (transposed = 0) or transposed solves (median of 5
  * timed runs after a warm-up), remember the fastest for solves of the same kind and
  * similar shape (used by tf_adjoint_step, whose solves are transposed, and by
  * tf_penta_solve with variant -1), and append a JSON line {arch, length, batch,
  * transposed, variant, block, ms: {...}} to cache_path (nullable). tf_autotune_load
  * reads such a file (entries of the current GPU architecture only; TF_EINVAL if there
- * are none). tf_autotune_choice returns the variant that would be used (0, 1 or 2). */
+ * are none). tf_autotune_choice returns the variant that would be used (0 ..= 3). */
 tf_status tf_autotune(int length, int batch, int transposed, const char *cache_path);
 tf_status tf_autotune_load(const char *cache_path);
 int tf_autotune_choice(int length, int batch, int transposed);

@@ -44,14 +44,16 @@ __device__ __forceinline__ Cell cell_glob(const double *u, int nx, int ny, int i
 }
 
 // Bands (a, b, c, d, e) of I + c J along direction DIR at every cell, stored
-// position-major for the stored-band solver: DIR 0 (y) as [j][i], DIR 1 (x) as [i][j].
-template <int DIR, bool P32>
+// position-major for the stored-band solver: DIR 0 (y) as [j][i], DIR 1 (x) as [i][j];
+// with LM (DIR 1) line-major as [j][i] for the whole-line row solver.
+template <int DIR, bool P32, bool LM = false>
 __global__ void __launch_bounds__(256) k_bands_store(int nx, int ny, double ids, double ids2, double k1, double k3,
                                                      Model M, const double *u, double *bands)
 {
-    // DIR 0: lanes along i; DIR 1: lanes along j (coalesced stores of the [i][j] layout)
+    // lanes along the contiguous index of the layout: i for [j][i], j for [i][j]
+    constexpr bool LANES_I = DIR == 0 || LM;
     const int a0 = blockIdx.x * 64 + (threadIdx.x & 63), b0 = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int i = DIR == 0 ? a0 : b0, j = DIR == 0 ? b0 : a0;
+    const int i = LANES_I ? a0 : b0, j = LANES_I ? b0 : a0;
     if (i >= nx || j >= ny) return;
     const int Np = DIR == 0 ? ny : nx;
     const int gp = DIR == 0 ? j : i;
@@ -71,7 +73,7 @@ __global__ void __launch_bounds__(256) k_bands_store(int nx, int ny, double ids,
     if (gp == Np - 1) { c += d; b += e; d = 0.0; e = 0.0; }
     else if (gp == Np - 2) { d += e; e = 0.0; }
     const size_t N = (size_t)nx * ny;
-    const size_t o = DIR == 0 ? (size_t)j * nx + i : (size_t)i * ny + j;
+    const size_t o = LANES_I ? (size_t)j * nx + i : (size_t)i * ny + j;
     bands[o] = a;
     bands[N + o] = b;
     bands[2 * N + o] = c;
@@ -613,8 +615,8 @@ tf_status afail(tf_status s, const std::string &msg)
         if (e_ != hipSuccess) return afail(TF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-enum Variant { V_PARTITIONED = 0, V_THOMAS = 1, V_PCR = 2, N_VARIANTS = 3 };
-const char *kVariantNames[] = {"partitioned", "thomas", "pcr"};
+enum Variant { V_PARTITIONED = 0, V_THOMAS = 1, V_PCR = 2, V_LINE = 3, N_VARIANTS = 4 };
+const char *kVariantNames[] = {"partitioned", "thomas", "pcr", "line"};
 
 // A solver choice: the variant and, for Thomas, the workgroup size (lines per block).
 struct Choice {
@@ -658,7 +660,9 @@ Choice pick_variant(int np, int nl, bool trans)
         const double d = std::fabs(std::log((double)kv.first.length / np)) + std::fabs(std::log((double)kv.first.batch / nl));
         if (d < best_d) { best_d = d; c = kv.second; found = true; }
     }
-    if (found && best_d < 0.7 && !(c.variant == V_PCR && np > tf::PCR_MAX)) return c;
+    if (found && best_d < 0.7 && !(c.variant == V_PCR && np > tf::PCR_MAX)
+        && !(c.variant == V_LINE && !tf::sbline_supported(np)))
+        return c;
     c.variant = nl >= 65536 ? V_THOMAS : V_PARTITIONED;
     c.block = 64;
     return c;
@@ -695,13 +699,19 @@ int xsweep_choice(int nx, int ny)
 
 namespace {
 
-// rowio: rhs and out line-major (partitioned variant, transposed MODE 0 solves only).
+// rowio: rhs and out line-major (transposed MODE 0 solves of the partitioned variant, and
+// of the whole-line variant, whose bands are then line-major too).
 tf_status sb_solve(Choice ch, bool trans, int mode, int nl, int np, const double *bands, const double *rhs,
                    double *out, unsigned long long *red, const Scratch &S, hipStream_t s, bool rowio = false)
 {
     tf::SBParams P{nl, np, bands, rhs, out, S.rel, S.ext, red};
-    if (rowio && (ch.variant != V_PARTITIONED || !trans || mode != 0))
-        return afail(TF_EINVAL, "line-major solves need the partitioned transposed MODE 0 variant");
+    if (rowio && ((ch.variant != V_PARTITIONED && ch.variant != V_LINE) || !trans || mode != 0))
+        return afail(TF_EINVAL, "line-major solves need a transposed MODE 0 partitioned or whole-line solve");
+    if (ch.variant == V_LINE) {
+        if (!tf::sbline_supported(np)) return afail(TF_EINVAL, "the whole-line solver needs 4 <= n <= 4096");
+        TF_AHIP(tf::launch_sbline(trans, !rowio, mode, nl, np, bands, rhs, out, red, s));
+        return TF_OK;
+    }
     if (ch.variant == V_PCR) {
         if (np > tf::PCR_MAX) return afail(TF_EINVAL, "cyclic reduction needs lines of at most 2048 cells");
         const dim3 g(nl), b(tf::PCR_THREADS);
@@ -904,7 +914,7 @@ size_t scratch_need(int variant, int n, int nlines)
     const size_t recs = (size_t)tf::seg_count(n) * nlines;
     if (variant == V_PARTITIONED) return recs * (tf::NREL + tf::NEXT + tf::NCHAIN);
     if (variant == V_THOMAS) return 3 * (size_t)n * nlines;
-    return 0; // cyclic reduction works in LDS
+    return 0; // cyclic reduction and the whole-line solver work in LDS
 }
 } // namespace
 
@@ -930,20 +940,28 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
     const double ids = 1.0 / v.ds, ids2 = ids * ids;
     const double k1 = c / v.ds, k3 = c / (v.ds * v.ds * v.ds * v.ds);
     hipStream_t s = v.stream;
-    // bands of I + c J_x (stored [i][j]) and I + c J_y (stored [j][i]) at u^{n+1}
+    // the x solves take the grid's x-sweep variant: whole rows in one kernel (bands of
+    // I + c J_x stored [j][i]) or else the tuned stored-band solver without that kernel
+    // (bands stored [i][j]); the y solves take the tuned variant
+    const bool rowx = v.xsweep == TF_XSWEEP_ROW && tf::sbline_supported(nx);
+    // bands of I + c J_x and I + c J_y (stored [j][i]) at u^{n+1}
     {
         const dim3 gy((nx + 63) / 64, (ny + 3) / 4), gx((ny + 63) / 64, (nx + 3) / 4), blk(256);
         if (v.M.p32) {
             tf::k_bands_store<0, true><<<gy, blk, 0, s>>>(nx, ny, ids, ids2, k1, k3, v.M, h_np1, B.by);
-            tf::k_bands_store<1, true><<<gx, blk, 0, s>>>(nx, ny, ids, ids2, k1, k3, v.M, h_np1, B.bx);
+            if (rowx) tf::k_bands_store<1, true, true><<<gy, blk, 0, s>>>(nx, ny, ids, ids2, k1, k3, v.M, h_np1, B.bx);
+            else tf::k_bands_store<1, true><<<gx, blk, 0, s>>>(nx, ny, ids, ids2, k1, k3, v.M, h_np1, B.bx);
         } else {
             tf::k_bands_store<0, false><<<gy, blk, 0, s>>>(nx, ny, ids, ids2, k1, k3, v.M, h_np1, B.by);
-            tf::k_bands_store<1, false><<<gx, blk, 0, s>>>(nx, ny, ids, ids2, k1, k3, v.M, h_np1, B.bx);
+            if (rowx) tf::k_bands_store<1, false, true><<<gy, blk, 0, s>>>(nx, ny, ids, ids2, k1, k3, v.M, h_np1, B.bx);
+            else tf::k_bands_store<1, false><<<gx, blk, 0, s>>>(nx, ny, ids, ids2, k1, k3, v.M, h_np1, B.bx);
         }
         TF_AHIP(hipGetLastError());
     }
     Scratch S{v.rel, v.ext, v.chain, B.work};
-    const Choice vx = pick_variant(nx, ny, true), vy = pick_variant(ny, nx, true);
+    Choice vx = pick_variant(nx, ny, true);
+    const Choice vy = pick_variant(ny, nx, true);
+    if (vx.variant == V_LINE) vx = Choice{};
     // initial guess mu = lambda^{n+1} (the solution for dt -> 0; only the number of
     // iterations depends on it)
     TF_AHIP(hipMemcpyAsync(B.mu, lambda_inout, N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -953,9 +971,12 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
         // r = lambda - (I + c J^T) mu
         // (the reduction words of this iteration's y solve are zeroed by the same kernel)
         if ((st = jdt(v, h_np1, B.mu, lambda_inout, 1.0, -1.0, -c, B.r, B, B.red)) != TF_OK) return st;
-        // (I + c J_x)^-T: rows as lines; the partitioned solver reads r and writes y row by
-        // row through LDS, the other variants work on the transposed layout [i][j]
-        if (vx.variant == V_PARTITIONED) {
+        // (I + c J_x)^-T: rows as lines; the whole-row kernel and the partitioned solver
+        // read r and write y row by row, the other variants work on the transposed layout
+        if (rowx) {
+            if ((st = sb_solve(Choice{V_LINE, 256}, true, 0, ny, nx, B.bx, B.r, B.y, nullptr, S, s, true)) != TF_OK)
+                return st;
+        } else if (vx.variant == V_PARTITIONED) {
             if ((st = sb_solve(vx, true, 0, ny, nx, B.bx, B.r, B.y, nullptr, S, s, true)) != TF_OK) return st;
         } else {
             if ((st = transpose(ny, nx, B.r, B.rT, s)) != TF_OK) return st;
@@ -1022,9 +1043,10 @@ tf_status tf_jacobian_apply_t(tf_grid *g, const double *u, const double *mu, dou
 tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *rhs, double *x, int transposed,
                          int variant, void *stream)
 {
-    if (nlines < 1 || n < 2 || bands == nullptr || rhs == nullptr || x == nullptr || variant < -1 || variant > 2)
+    if (nlines < 1 || n < 2 || bands == nullptr || rhs == nullptr || x == nullptr || variant < -1 || variant > 3)
         return afail(TF_EINVAL, "bad argument");
     if (variant == V_PCR && n > tf::PCR_MAX) return afail(TF_EINVAL, "cyclic reduction needs n <= 2048");
+    if (variant == V_LINE && !tf::sbline_supported(n)) return afail(TF_EINVAL, "the whole-line solver needs 4 <= n <= 4096");
     hipStream_t s = (hipStream_t)stream;
     const size_t recs = (size_t)tf::seg_count(n) * nlines;
     Scratch S;
@@ -1051,9 +1073,10 @@ tf_status tf_penta_solve(int nlines, int n, const double *bands, const double *r
 tf_status tf_penta_solve_noalloc(int nlines, int n, const double *bands, const double *rhs, double *x,
                                  int transposed, int variant, void *stream)
 {
-    if (nlines < 1 || n < 2 || bands == nullptr || rhs == nullptr || x == nullptr || variant < -1 || variant > 2)
+    if (nlines < 1 || n < 2 || bands == nullptr || rhs == nullptr || x == nullptr || variant < -1 || variant > 3)
         return afail(TF_EINVAL, "bad argument");
     if (variant == V_PCR && n > tf::PCR_MAX) return afail(TF_EINVAL, "cyclic reduction needs n <= 2048");
+    if (variant == V_LINE && !tf::sbline_supported(n)) return afail(TF_EINVAL, "the whole-line solver needs 4 <= n <= 4096");
     Choice c;
     if (variant < 0) {
         c = pick_variant(n, nlines, transposed != 0);
@@ -1098,7 +1121,7 @@ tf_status tf_autotune(int length, int batch, int transposed, const char *cache_p
               && hipMalloc(&S.work, 3 * N * sizeof(double)) == hipSuccess;
     tf_status st = ok ? TF_OK : afail(TF_ENOMEM, "autotune allocation failed");
     // candidates: partitioned; Thomas with 64, 128, 256 lines per block; cyclic reduction
-    // (lines of at most PCR_MAX cells)
+    // (lines of at most PCR_MAX cells); whole lines in one kernel (lines of 4 ..= 4096 cells)
     std::vector<Choice> cands;
     std::vector<std::string> names;
     cands.push_back({V_PARTITIONED, 64});
@@ -1110,6 +1133,10 @@ tf_status tf_autotune(int length, int batch, int transposed, const char *cache_p
     if (length <= tf::PCR_MAX) {
         cands.push_back({V_PCR, tf::PCR_THREADS});
         names.push_back("pcr");
+    }
+    if (tf::sbline_supported(length)) {
+        cands.push_back({V_LINE, 256});
+        names.push_back("line");
     }
     std::vector<double> ms(cands.size(), 1e30);
     if (st == TF_OK) {
@@ -1317,7 +1344,7 @@ tf_status tf_autotune_load(const char *cache_path)
             ++loaded;
             continue;
         }
-        c.variant = V == "thomas" ? V_THOMAS : (V == "pcr" ? V_PCR : V_PARTITIONED);
+        c.variant = V == "thomas" ? V_THOMAS : (V == "pcr" ? V_PCR : (V == "line" ? V_LINE : V_PARTITIONED));
         c.block = Bs.empty() ? 64 : std::stoi(Bs);
         t.best[{std::stoi(L), std::stoi(Bt), Tr.empty() ? 0 : (std::stoi(Tr) != 0)}] = c;
         ++loaded;

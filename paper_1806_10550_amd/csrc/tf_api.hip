@@ -446,6 +446,7 @@ bool grid_view(const tf_grid *g, GridView *v)
     v->rel = g->rel;
     v->ext = g->ext;
     v->chain = g->chain;
+    v->xsweep = g->xsweep;
     return true;
 }
 } // namespace tf_detail

@@ -156,6 +156,12 @@ hipError_t launch_pass(int dir, bool solve, const PassParams &p, hipStream_t s);
 bool xrow_supported(int nx);
 int xrow_blocks(int nx, int ny);           // workgroups of one launch (= mass records)
 hipError_t launch_xrow(const PassParams &p, hipStream_t s);
+// Stored-band solves of whole lines (4 ..= XR_ROW4_MAX_NX cells) in one kernel: pm true
+// position-major (plain or transposed; mode 0 out = x, mode 1 out += x with the maxima in
+// red[0..1]), pm false line-major (transposed, mode 0 only).
+bool sbline_supported(int np);
+hipError_t launch_sbline(bool trans, bool pm, int mode, int nl, int np, const double *bands, const double *rhs,
+                         double *out, unsigned long long *red, hipStream_t s);
 // x-sweep variant for a film of nx x ny cells (0: partitioned, 1: whole-row): the autotuned
 // choice for the nearest shape, else the built-in rule (tf_adjoint.hip).
 int xsweep_choice(int nx, int ny);
@@ -192,6 +198,7 @@ struct GridView {
     tf::Model M;
     hipStream_t stream;
     double *rel, *ext, *chain;
+    int xsweep;               // x-sweep variant (TF_XSWEEP_PARTITIONED / TF_XSWEEP_ROW)
 };
 bool grid_view(const tf_grid *g, GridView *v);   // false if the model is not set
 void release_adjoint(const tf_grid *g);           // frees adjoint scratch of a grid

@@ -186,6 +186,128 @@ __device__ __forceinline__ void rec_split(double *rec, int S, int a, int c)
     rec[3 * S + c] = to1;
 }
 
+// LU step at position k of a lane's sub-segment with the outer unknowns l1 = x_{p0-2},
+// l2 = x_{p0-1} kept symbolic (z: constant part, ph: coefficient of l1, ps: of l2); the
+// factors of every position stay in the arrays for the back-substitution.
+template <int CPL>
+__device__ __forceinline__ void xr_elim(int k, const Band &B, double rhs, double (&fa)[CPL], double (&fb)[CPL],
+                                        double (&fz)[CPL], double (&fph)[CPL], double (&fps)[CPL])
+{
+    const double al2 = k >= 2 ? fa[k - 2] : 0.0, be2 = k >= 2 ? fb[k - 2] : 0.0;
+    const double al1 = k >= 1 ? fa[k - 1] : 0.0, be1 = k >= 1 ? fb[k - 1] : 0.0;
+    const double z2 = k >= 2 ? fz[k - 2] : 0.0, z1 = k >= 1 ? fz[k - 1] : 0.0;
+    // rows p0-2 and p0-1 stand for the outer unknowns l1 (ph = 1) and l2 (ps = 1)
+    const double ph2 = k >= 2 ? fph[k - 2] : (k == 0 ? 1.0 : 0.0), ph1 = k >= 1 ? fph[k - 1] : 0.0;
+    const double ps2 = k >= 2 ? fps[k - 2] : (k == 1 ? 1.0 : 0.0), ps1 = k >= 1 ? fps[k - 1] : 1.0;
+    const double gam = B.b - B.a * al2;
+    const double mu = B.c - B.a * be2 - gam * al1;
+    const double rm = rcp_pivot(mu);
+    fa[k] = (B.d - gam * be1) * rm;
+    fb[k] = B.e * rm;
+    fz[k] = (rhs - B.a * z2 - gam * z1) * rm;
+    fph[k] = (-B.a * ph2 - gam * ph1) * rm;
+    fps[k] = (-B.a * ps2 - gam * ps1) * rm;
+}
+
+// The relation record of slot s from the factors of its sub-segment (Rel layout, field f at
+// rec[f * S + s]). Top pair: x_{p0} = sum_k g_k Z_k, x_{p0+1} = sum_k h_k Z_k with g, h the
+// first two rows of the inverse of the unit upper factor (g_k = -al_{k-1} g_{k-1} -
+// be_{k-2} g_{k-2}) and Z_k = z_k + ph_k l1 + ps_k l2 the eliminated right-hand sides;
+// bottom pair x_{e-1} = Z_{e-1} - al1 r1 - be1 r2, x_{e-2} = Z_{e-2} - al2 x_{e-1} - be2 r1.
+template <int CPL>
+__device__ __forceinline__ void xr_record(double *rec, int S, int s, const double (&fa)[CPL], const double (&fb)[CPL],
+                                          const double (&fz)[CPL], const double (&fph)[CPL], const double (&fps)[CPL])
+{
+    double g1 = 0.0, g2 = 0.0, h1 = 0.0, h2 = 0.0;
+    double sgz = 0.0, sgph = 0.0, sgps = 0.0, shz = 0.0, shph = 0.0, shps = 0.0;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const double gg = k == 0 ? 1.0 : -fa[k - 1] * g1 - (k >= 2 ? fb[k - 2] : 0.0) * g2;
+        const double hh = k == 1 ? 1.0 : (k == 0 ? 0.0 : -fa[k - 1] * h1 - (k >= 2 ? fb[k - 2] : 0.0) * h2);
+        sgz += gg * fz[k]; sgph += gg * fph[k]; sgps += gg * fps[k];
+        shz += hh * fz[k]; shph += hh * fph[k]; shps += hh * fps[k];
+        g2 = g1; g1 = gg; h2 = h1; h1 = hh;
+    }
+    constexpr int L = CPL - 1;
+    double *r = rec + s;
+    r[0 * S] = sgz; r[1 * S] = sgph; r[2 * S] = sgps;
+    r[3 * S] = -g2 * fb[L - 1] - g1 * fa[L]; r[4 * S] = -g1 * fb[L];
+    r[5 * S] = shz; r[6 * S] = shph; r[7 * S] = shps;
+    r[8 * S] = -h2 * fb[L - 1] - h1 * fa[L]; r[9 * S] = -h1 * fb[L];
+    r[10 * S] = fz[L - 1] - fa[L - 1] * fz[L];
+    r[11 * S] = fph[L - 1] - fa[L - 1] * fph[L];
+    r[12 * S] = fps[L - 1] - fa[L - 1] * fps[L];
+    r[13 * S] = -fb[L - 1] + fa[L - 1] * fa[L];
+    r[14 * S] = fa[L - 1] * fb[L];
+    r[15 * S] = fz[L]; r[16 * S] = fph[L]; r[17 * S] = fps[L]; r[18 * S] = -fa[L]; r[19 * S] = -fb[L];
+}
+
+// Tree over the S records of a row (called by every thread of the workgroup; tr: the
+// thread's index within its row group, row_ok: the group holds a row). Level l merges the
+// blocks starting at slots b * 2^l and b * 2^l + 2^(l-1); merge b is done by thread b of the
+// row group, so only the first waves work at the low levels and wave 0 alone at the top
+// (nm <= 64 merges: no workgroup barrier needed there, only ordering of this wave's LDS
+// accesses). On return, fields 0..3 of slot s hold the outer pairs of sub-segment s.
+__device__ __forceinline__ void xr_tree(double *rec, int S, int tr, bool row_ok)
+{
+    int levels = 0;
+    while ((1 << levels) < S) ++levels;
+    auto nmerge = [&](int l) { const int half = 1 << (l - 1); return (S - half + 2 * half - 1) / (2 * half); };
+    int lw = levels + 1; // first level done by wave 0 alone
+    for (int l = 1; l <= levels; ++l)
+        if (nmerge(l) <= 64) { lw = l; break; }
+    for (int l = 1; l < lw; ++l) {
+        const int half = 1 << (l - 1);
+        if (row_ok && tr < nmerge(l)) rec_merge(rec, S, tr * 2 * half, tr * 2 * half + half);
+        __syncthreads();
+    }
+    if (row_ok && tr < 64) {
+        for (int l = lw; l <= levels; ++l) {
+            const int half = 1 << (l - 1);
+            if (tr < nmerge(l)) rec_merge(rec, S, tr * 2 * half, tr * 2 * half + half);
+            wave_lds_sync();
+        }
+        // the row's outer pairs are the ghost-folded ends: zero
+        if (tr == 0) { rec[0 * S] = 0.0; rec[1 * S] = 0.0; rec[2 * S] = 0.0; rec[3 * S] = 0.0; }
+        wave_lds_sync();
+        for (int l = levels; l >= lw; --l) {
+            const int half = 1 << (l - 1);
+            if (tr < nmerge(l)) rec_split(rec, S, tr * 2 * half, tr * 2 * half + half);
+            wave_lds_sync();
+        }
+    }
+    __syncthreads();
+    for (int l = lw - 1; l >= 1; --l) {
+        const int half = 1 << (l - 1);
+        if (row_ok && tr < nmerge(l)) rec_split(rec, S, tr * 2 * half, tr * 2 * half + half);
+        __syncthreads();
+    }
+}
+
+// Back-substitution of slot s from its outer pairs (fields 0..3 of the slot after the tree);
+// the coefficient ps of l2 waits in the LDS slot of each position (parked there before the
+// tree) and the solution replaces it.
+// (lnear: the lane may hold padding positions gp < 0, which have no slot)
+template <int CPL>
+__device__ __forceinline__ void xr_backsub(const double *rec, int S, int s, int p0, bool lnear, double *slots,
+                                           const double (&fa)[CPL], const double (&fb)[CPL], const double (&fz)[CPL],
+                                           const double (&fph)[CPL])
+{
+    const double l1 = rec[0 * S + s], l2 = rec[1 * S + s];
+    double x1 = rec[2 * S + s], x2 = rec[3 * S + s];
+#pragma unroll
+    for (int k = CPL - 1; k >= 0; --k) {
+        const int gp = p0 + k;
+        if (!lnear || gp >= 0) {
+            double *slot = slots + xr_pad(gp);
+            const double v = fz[k] + fph[k] * l1 + *slot * l2 - fa[k] * x1 - fb[k] * x2;
+            *slot = v;
+            x2 = x1;
+            x1 = v;
+        }
+    }
+}
+
 // ---- the kernel body -------------------------------------------------------------------
 // Lane s of a row owns the XR_CPL positions p0 + k, p0 = nx - XR_CPL (S - s), k < XR_CPL.
 // Positions before the row (only in lane 0, when XR_CPL does not divide nx) are identity
@@ -282,20 +404,7 @@ __device__ __forceinline__ void xrow_body(const PassParams &p, const XRowGeom &g
                     fold_left(B, 1);
                 }
             }
-            const double al2 = k >= 2 ? fa[k - 2] : 0.0, be2 = k >= 2 ? fb[k - 2] : 0.0;
-            const double al1 = k >= 1 ? fa[k - 1] : 0.0, be1 = k >= 1 ? fb[k - 1] : 0.0;
-            const double z2 = k >= 2 ? fz[k - 2] : 0.0, z1 = k >= 1 ? fz[k - 1] : 0.0;
-            // rows p0-2 and p0-1 stand for the outer unknowns l1 (ph = 1) and l2 (ps = 1)
-            const double ph2 = k >= 2 ? fph[k - 2] : (k == 0 ? 1.0 : 0.0), ph1 = k >= 1 ? fph[k - 1] : 0.0;
-            const double ps2 = k >= 2 ? fps[k - 2] : (k == 1 ? 1.0 : 0.0), ps1 = k >= 1 ? fps[k - 1] : 1.0;
-            const double gam = B.b - B.a * al2;
-            const double mu = B.c - B.a * be2 - gam * al1;
-            const double rm = rcp_pivot(mu);
-            fa[k] = (B.d - gam * be1) * rm;
-            fb[k] = B.e * rm;
-            fz[k] = (rhs - B.a * z2 - gam * z1) * rm;
-            fph[k] = (-B.a * ph2 - gam * ph1) * rm;
-            fps[k] = (-B.a * ps2 - gam * ps1) * rm;
+            xr_elim(k, B, rhs, fa, fb, fz, fph, fps);
             c0 = cp;
             fm = fp;
         }
@@ -304,92 +413,15 @@ __device__ __forceinline__ void xrow_body(const PassParams &p, const XRowGeom &g
                      // row's space holds one factor array until the back-substitution
     double *const rec = sX;
     if (act) {
-        // top pair: x_{p0} = sum_k g_k Z_k, x_{p0+1} = sum_k h_k Z_k with g, h the first two
-        // rows of the inverse of the unit upper factor (g_k = -al_{k-1} g_{k-1} - be_{k-2}
-        // g_{k-2}) and Z_k = z_k + ph_k l1 + ps_k l2 the eliminated right-hand sides
-        double g1 = 0.0, g2 = 0.0, h1 = 0.0, h2 = 0.0;
-        double sgz = 0.0, sgph = 0.0, sgps = 0.0, shz = 0.0, shph = 0.0, shps = 0.0;
-#pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            const double gg = k == 0 ? 1.0 : -fa[k - 1] * g1 - (k >= 2 ? fb[k - 2] : 0.0) * g2;
-            const double hh = k == 1 ? 1.0 : (k == 0 ? 0.0 : -fa[k - 1] * h1 - (k >= 2 ? fb[k - 2] : 0.0) * h2);
-            sgz += gg * fz[k]; sgph += gg * fph[k]; sgps += gg * fps[k];
-            shz += hh * fz[k]; shph += hh * fph[k]; shps += hh * fps[k];
-            g2 = g1; g1 = gg; h2 = h1; h1 = hh;
-        }
-        // the relation record (Rel layout, field f of slot s at rec[f * S + s]):
-        // bottom pair x_{e-1} = Z_{e-1} - al1 r1 - be1 r2, x_{e-2} = Z_{e-2} - al2 x_{e-1} - be2 r1
-        constexpr int L = CPL - 1;
-        double *r = rec + s;
-        r[0 * S] = sgz; r[1 * S] = sgph; r[2 * S] = sgps;
-        r[3 * S] = -g2 * fb[L - 1] - g1 * fa[L]; r[4 * S] = -g1 * fb[L];
-        r[5 * S] = shz; r[6 * S] = shph; r[7 * S] = shps;
-        r[8 * S] = -h2 * fb[L - 1] - h1 * fa[L]; r[9 * S] = -h1 * fb[L];
-        r[10 * S] = fz[L - 1] - fa[L - 1] * fz[L];
-        r[11 * S] = fph[L - 1] - fa[L - 1] * fph[L];
-        r[12 * S] = fps[L - 1] - fa[L - 1] * fps[L];
-        r[13 * S] = -fb[L - 1] + fa[L - 1] * fa[L];
-        r[14 * S] = fa[L - 1] * fb[L];
-        r[15 * S] = fz[L]; r[16 * S] = fph[L]; r[17 * S] = fps[L]; r[18 * S] = -fa[L]; r[19 * S] = -fb[L];
+        xr_record(rec, S, s, fa, fb, fz, fph, fps);
 #pragma unroll
         for (int k = 0; k < CPL; ++k)
             if (!lnear || p0 + k >= 0) sU[xr_pad(p0 + k)] = fps[k];
     }
     __syncthreads();
-
-    // Tree over the S records of the row. Level l merges the blocks starting at slots
-    // b * 2^l and b * 2^l + 2^(l-1); merge b is done by thread b of the row group, so only
-    // the first waves work at the low levels and wave 0 alone at the top (nm <= 64 merges:
-    // no workgroup barrier needed there, only ordering of this wave's LDS accesses).
-    int levels = 0;
-    while ((1 << levels) < S) ++levels;
-    auto nmerge = [&](int l) { const int half = 1 << (l - 1); return (S - half + 2 * half - 1) / (2 * half); };
-    int lw = levels + 1; // first level done by wave 0 alone
-    for (int l = 1; l <= levels; ++l)
-        if (nmerge(l) <= 64) { lw = l; break; }
-    for (int l = 1; l < lw; ++l) {
-        const int half = 1 << (l - 1);
-        if (row_ok && tr < nmerge(l)) rec_merge(rec, S, tr * 2 * half, tr * 2 * half + half);
-        __syncthreads();
-    }
-    if (row_ok && s < 64) {
-        for (int l = lw; l <= levels; ++l) {
-            const int half = 1 << (l - 1);
-            if (tr < nmerge(l)) rec_merge(rec, S, tr * 2 * half, tr * 2 * half + half);
-            wave_lds_sync();
-        }
-        // the row's outer pairs are the ghost-folded ends: zero
-        if (tr == 0) { rec[0 * S] = 0.0; rec[1 * S] = 0.0; rec[2 * S] = 0.0; rec[3 * S] = 0.0; }
-        wave_lds_sync();
-        for (int l = levels; l >= lw; --l) {
-            const int half = 1 << (l - 1);
-            if (tr < nmerge(l)) rec_split(rec, S, tr * 2 * half, tr * 2 * half + half);
-            wave_lds_sync();
-        }
-    }
-    __syncthreads();
-    for (int l = lw - 1; l >= 1; --l) {
-        const int half = 1 << (l - 1);
-        if (row_ok && tr < nmerge(l)) rec_split(rec, S, tr * 2 * half, tr * 2 * half + half);
-        __syncthreads();
-    }
-
+    xr_tree(rec, S, tr, row_ok);
     // back-substitution from the outer pairs; v replaces the parked factor in the u row
-    if (act) {
-        const double l1 = rec[0 * S + s], l2 = rec[1 * S + s];
-        double x1 = rec[2 * S + s], x2 = rec[3 * S + s];
-#pragma unroll
-        for (int k = CPL - 1; k >= 0; --k) {
-            const int gp = p0 + k;
-            if (!lnear || gp >= 0) {
-                double *slot = sU + xr_pad(gp);
-                const double v = fz[k] + fph[k] * l1 + *slot * l2 - fa[k] * x1 - fb[k] * x2;
-                *slot = v;
-                x2 = x1;
-                x1 = v;
-            }
-        }
-    }
+    if (act) xr_backsub(rec, S, s, p0, lnear, sU, fa, fb, fz, fph);
     __syncthreads();
 
     // output: u_{k+1} = u_k + v, update ratio, flags, mass diagnostic (coalesced)
@@ -518,6 +550,126 @@ hipError_t launch_xrow_ens(int km, const EnsParams &e, hipStream_t s)
     case KM_NLC: k_xrow_ens<KM_NLC><<<grid, block, 0, s>>>(e); break;
     default: k_xrow_ens<KM_POLYMER><<<grid, block, 0, s>>>(e); break;
     }
+    return hipGetLastError();
+}
+
+// ---- stored-band whole-line solve -------------------------------------------------------
+// A x = r (TRANS: A^T x = r) for nl lines of np cells with the five bands a..e of A stored
+// per line: line-major (PM false: element (line j, position i) at j np + i; the row solves
+// of the adjoint's preconditioner) or position-major (PM true: at i nl + j; the layout of
+// tf_penta_solve and of the adjoint's column solves), bands back to back (band k at
+// k nl np). MODE 0: out = x; MODE 1: out += x and red[0], red[1] take max|x|, max|out|
+// (atomic maxima of the bit patterns). One kernel instead of the partitioned solver's three:
+// the elimination, relation records, tree and back-substitution are those of the forward
+// whole-row sweep. Row p of A^T is (e_{p-2}, d_{p-1}, c_p, b_{p+1}, a_{p+2}); entries that
+// reach outside the line are taken as zero. Padding positions before the line (lane 0, when
+// XR_CPL does not divide np) are identity rows with a zero right-hand side, and the first
+// real rows have no coupling to them.
+template <bool TRANS, bool PM, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_sbline(int nl, int np, const double *bands, const double *rhs, double *out, unsigned long long *red, XRowGeom g,
+         int nblocks)
+{
+    __shared__ double lds[xr_lds(4)];
+    __shared__ double sRed[4][2];
+    constexpr int CPL = XR_CPL;
+    const int rb = xcd_tile(blockIdx.x, nblocks);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rg = wave / g.W;                       // line group of this wave (uniform)
+    const int s = (wave - rg * g.W) * 64 + lane;     // slot (sub-segment) of this lane in its line
+    const int nthr = 64 * g.W;
+    const int j = rb * g.R + rg;
+    const bool row_ok = rg < g.R && j < nl;
+    double *const sV = lds + (size_t)rg * (g.pu + g.p2); // parked factor, then the solution
+    double *const rec = sV + g.pu;
+    const int S = g.S;
+    const bool act = row_ok && s < S;
+    const int p0 = np - CPL * (S - s);
+    const bool lnear = p0 <= 1;
+    const size_t N = (size_t)nl * np;
+    // element (position q, this line), 0 <= q < np
+    auto at = [&](int q) -> size_t { return PM ? (size_t)q * nl + j : (size_t)j * np + q; };
+    double fa[CPL], fb[CPL], fz[CPL], fph[CPL], fps[CPL];
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            const int q = p0 + k;
+            const bool real = q >= 0;
+            // every load stays inside the line (clamped position); entries outside it are
+            // selected away afterwards
+            double va, vb, vc, vd, ve;
+            if (TRANS) {
+                va = bands[4 * N + at(max(q - 2, 0))];
+                vb = bands[3 * N + at(max(q - 1, 0))];
+                vc = bands[2 * N + at(max(q, 0))];
+                vd = bands[N + at(min(max(q + 1, 0), np - 1))];
+                ve = bands[at(min(max(q + 2, 0), np - 1))];
+            } else {
+                const size_t o = at(max(q, 0));
+                va = bands[o]; vb = bands[N + o]; vc = bands[2 * N + o]; vd = bands[3 * N + o]; ve = bands[4 * N + o];
+            }
+            const double rr = rhs[at(max(q, 0))];
+            Band B;
+            B.a = q >= 2 ? va : 0.0;
+            B.b = q >= 1 ? vb : 0.0;
+            B.c = real ? vc : 1.0;
+            B.d = real && q + 1 < np ? vd : 0.0;
+            B.e = real && q + 2 < np ? ve : 0.0;
+            xr_elim(k, B, real ? rr : 0.0, fa, fb, fz, fph, fps);
+        }
+        xr_record(rec, S, s, fa, fb, fz, fph, fps);
+#pragma unroll
+        for (int k = 0; k < CPL; ++k)
+            if (!lnear || p0 + k >= 0) sV[xr_pad(p0 + k)] = fps[k];
+    }
+    __syncthreads();
+    xr_tree(rec, S, s, row_ok);
+    if (act) xr_backsub(rec, S, s, p0, lnear, sV, fa, fb, fz, fph);
+    __syncthreads();
+    double xm = 0.0, om = 0.0;
+    if (row_ok) {
+        for (int i = s; i < np; i += nthr) {
+            const double x = sV[xr_pad(i)];
+            const size_t o = at(i);
+            if (MODE == 0) {
+                out[o] = x;
+            } else {
+                const double v = out[o] + x;
+                out[o] = v;
+                xm = max_nan(xm, fabs(x));
+                om = max_nan(om, fabs(v));
+            }
+        }
+    }
+    if (MODE == 1) {
+        const double wx = wave_max_nan(xm), wo = wave_max_nan(om);
+        if (lane == 0) { sRed[wave][0] = wx; sRed[wave][1] = wo; }
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0.0, b = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a = max_nan(a, sRed[w][0]); b = max_nan(b, sRed[w][1]); }
+            atomicMax(&red[0], (unsigned long long)__double_as_longlong(a));
+            atomicMax(&red[1], (unsigned long long)__double_as_longlong(b));
+        }
+    }
+}
+
+bool sbline_supported(int np) { return np <= XR_ROW4_MAX_NX && xrow_supported(np); }
+
+hipError_t launch_sbline(bool trans, bool pm, int mode, int nl, int np, const double *bands, const double *rhs,
+                         double *out, unsigned long long *red, hipStream_t s)
+{
+    if (nl < 1 || !sbline_supported(np) || (mode == 1 && red == nullptr) || (!pm && (!trans || mode != 0)))
+        return hipErrorInvalidValue;
+    const XRowGeom g = xrow_geom(np); // 4-wave workgroups for lines of at most XR_ROW4_MAX_NX cells
+    const int nb = (nl + g.R - 1) / g.R;
+    const dim3 grid(nb), block(64 * g.W * g.R);
+    if (!pm) k_sbline<true, false, 0><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb);
+    else if (trans && mode == 0) k_sbline<true, true, 0><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb);
+    else if (trans) k_sbline<true, true, 1><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb);
+    else if (mode == 0) k_sbline<false, true, 0><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb);
+    else k_sbline<false, true, 1><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb);
     return hipGetLastError();
 }
 

@@ -421,8 +421,8 @@ class Ensemble:
         return info.as_dict()
 
 
-VARIANTS = {"auto": -1, "partitioned": 0, "thomas": 1, "pcr": 2}
-VARIANT_NAMES = ["partitioned", "thomas", "pcr"]
+VARIANTS = {"auto": -1, "partitioned": 0, "thomas": 1, "pcr": 2, "line": 3}
+VARIANT_NAMES = ["partitioned", "thomas", "pcr", "line"]
 
 
 def penta_solve(bands, rhs, x, transposed=False, variant="auto", stream=None):

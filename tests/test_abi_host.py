@@ -63,9 +63,14 @@ def test_penta_solve_validates_before_allocating(L):
     p = C.c_void_p(16)  # never dereferenced: validation fails first
     assert L.tf_penta_solve(0, 8, p, p, p, 0, 0, None) == TF_EINVAL
     assert L.tf_penta_solve(4, 1, p, p, p, 0, 0, None) == TF_EINVAL
-    assert L.tf_penta_solve(4, 8, p, p, p, 0, 3, None) == TF_EINVAL
+    assert L.tf_penta_solve(4, 8, p, p, p, 0, 4, None) == TF_EINVAL
     assert L.tf_penta_solve(4, 4096, p, p, p, 0, 2, None) == TF_EINVAL
     assert b"2048" in L.tf_last_error()
+    # the whole-line variant takes lines of 4 ..= 4096 cells
+    assert L.tf_penta_solve(4, 3, p, p, p, 1, 3, None) == TF_EINVAL
+    assert L.tf_penta_solve(4, 4097, p, p, p, 1, 3, None) == TF_EINVAL
+    assert b"4096" in L.tf_last_error()
+    assert L.tf_penta_solve_noalloc(4, 4097, p, p, p, 1, 3, None) == TF_EINVAL
 
 
 def test_autotune_arguments_and_default_choice(L, tmp_path):

@@ -10,7 +10,7 @@ import torch
 
 from paper_1806_10550_amd import synth
 from paper_1806_10550_amd.adjoint import rollout
-from paper_1806_10550_amd.lib import Grid, autotune, autotune_choice, autotune_load, penta_solve
+from paper_1806_10550_amd.lib import Grid, TFError, autotune, autotune_choice, autotune_load, penta_solve
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -69,13 +69,18 @@ def _bands(n, nl, seed, dominant=True):
     return b
 
 
-@pytest.mark.parametrize("n,nl", [(2, 3), (5, 7), (64, 64), (65, 130), (200, 33), (1000, 5), (2047, 3)])
+@pytest.mark.parametrize("n,nl", [(2, 3), (5, 7), (64, 64), (65, 130), (200, 33), (1000, 5), (2047, 3), (4096, 2)])
 @pytest.mark.parametrize("transposed", [False, True])
-@pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr"])
+@pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr", "line"])
 def test_penta_solve_matches_oracle(orc, n, nl, transposed, variant):
     b = _bands(n, nl, seed=n * 7 + nl)
     rhs = np.random.default_rng(n + nl).standard_normal((n, nl))
     x = torch.empty((n, nl), dtype=torch.float64, device=DEV)
+    if (variant == "line" and n < 4) or (variant == "pcr" and n > 2048):
+        # outside the variant's range of line lengths: refused before any launch
+        with pytest.raises(TFError):
+            penta_solve(gpu(b), gpu(rhs), x, transposed=transposed, variant=variant)
+        return
     penta_solve(gpu(b), gpu(rhs), x, transposed=transposed, variant=variant)
     got = x.cpu().numpy()
     for l in range(nl):
@@ -86,7 +91,7 @@ def test_penta_solve_matches_oracle(orc, n, nl, transposed, variant):
         assert np.max(np.abs(got[:, l] - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), l
 
 
-@pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr"])
+@pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr", "line"])
 def test_transposed_solve_dot_product(variant):
     """<w, A^-1 r> = <A^-T w, r> with both solves on the GPU (plain and transposed)."""
     n, nl = 130, 70
@@ -103,7 +108,7 @@ def test_transposed_solve_dot_product(variant):
     assert np.all(np.abs(lhs - rhs) <= 1e-12 * scale)
 
 
-@pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr"])
+@pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr", "line"])
 def test_penta_solve_on_model_bands(orc, variant):
     """Real (I + c J_x) systems of a noisy film (not diagonally dominant)."""
     nx, ny = 300, 40
@@ -133,6 +138,28 @@ def test_adjoint_step_matches_oracle(orc, theta):
     gk, it = g.adjoint_step(gpu(un), gpu(unp1), dt, lg, tol=1e-14)
     got = lg.cpu().numpy()
     assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+    assert gk == pytest.approx(gk_ref, rel=1e-9)
+
+
+@pytest.mark.parametrize("xsweep", ["partitioned", "row"])
+@pytest.mark.parametrize("nx,ny", [(37, 23), (130, 67), (300, 41), (1030, 9)])
+def test_adjoint_x_solve_variants_match_oracle(orc, xsweep, nx, ny):
+    """The adjoint's transposed row solves take the grid's x-sweep variant: whole rows in one
+    kernel (rows whose first sub-segment is ragged, several rows per workgroup, up to 4
+    waves per row) or the partitioned solver. One adjoint step of each against the oracle."""
+    ds, dt = 0.67347, 0.1
+    un = synth.noise_film(nx, ny, seed=12, amp=0.01)
+    M = orc.Model()
+    unp1, res = orc.step(M, orc.Scheme(tol=1e-14), un, ds, dt)
+    assert res.status == orc.OK
+    lam = np.random.default_rng(13).standard_normal((ny, nx))
+    ref, gk_ref, _ = orc.adjoint_step(M, un, unp1, lam, ds, dt, 1.0, tol=1e-14)
+    g = grid(nx, ny, ds)
+    g.set_xsweep(xsweep)
+    assert g.xsweep() == xsweep
+    lg = gpu(lam)
+    gk, _ = g.adjoint_step(gpu(un), gpu(unp1), dt, lg, tol=1e-14)
+    assert np.max(np.abs(lg.cpu().numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
     assert gk == pytest.approx(gk_ref, rel=1e-9)
 
 
@@ -251,10 +278,10 @@ def test_full_size_rollout_gradient_matches_finite_differences():
 def test_autotune_cache_roundtrip(tmp_path):
     path = str(tmp_path / "tune.jsonl")
     choice = autotune(512, 512, path)
-    assert choice in ("partitioned", "thomas", "pcr")
+    assert choice in ("partitioned", "thomas", "pcr", "line")
     rec = json.loads(open(path).read().strip().splitlines()[-1])
     assert rec["length"] == 512 and rec["batch"] == 512 and rec["variant"] == choice
-    assert set(rec["ms"]) == {"partitioned", "thomas/64", "thomas/128", "thomas/256", "pcr"}
+    assert set(rec["ms"]) == {"partitioned", "thomas/64", "thomas/128", "thomas/256", "pcr", "line"}
     assert all(math.isfinite(v) for v in rec["ms"].values())
     best = min(rec["ms"], key=rec["ms"].get)
     assert best.split("/")[0] == choice
@@ -265,8 +292,12 @@ def test_autotune_cache_roundtrip(tmp_path):
     # long lines: no cyclic reduction candidate; transposed solves are tuned separately
     ct = autotune(4096, 8, path, transposed=True)
     rec = json.loads(open(path).read().strip().splitlines()[-1])
-    assert "pcr" not in rec["ms"] and rec["length"] == 4096 and rec["transposed"] == 1
+    assert "pcr" not in rec["ms"] and "line" in rec["ms"] and rec["length"] == 4096 and rec["transposed"] == 1
     assert autotune_choice(4096, 8, transposed=True) == ct
+    # beyond 4096 cells the whole-line kernel is no candidate either
+    autotune(4100, 4, path, transposed=True)
+    rec = json.loads(open(path).read().strip().splitlines()[-1])
+    assert set(rec["ms"]) == {"partitioned", "thomas/64", "thomas/128", "thomas/256"}
 
 
 def test_pcr_rejects_long_lines():

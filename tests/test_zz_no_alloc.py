@@ -29,7 +29,7 @@ def _case(n, nl, seed):
     return _bands(n, nl, seed), torch.from_numpy(rng.standard_normal((n, nl))).to(DEV)
 
 
-@pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr", "auto"])
+@pytest.mark.parametrize("variant", ["partitioned", "thomas", "pcr", "line", "auto"])
 @pytest.mark.parametrize("transposed", [False, True])
 def test_noalloc_equals_penta_solve_twice(variant, transposed):
     for (n, nl), seed in (((1000, 300), 3), ((130, 70), 4)):   # second call smaller
