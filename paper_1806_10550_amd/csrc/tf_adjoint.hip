@@ -470,11 +470,9 @@ __global__ void __launch_bounds__(PCR_THREADS) k_sb_pcr(SBParams P)
 //   xi_c    = sum_f omega_f A_f (+1 if c = R, -1 if c = L) / ds
 // and L the cell-centred Laplacian (symmetric under the even reflection).
 template <bool P32>
-__global__ void __launch_bounds__(256) k_jdt_xi(int nx, int ny, double ids, double ids2, Model M, const double *u,
-                                                const double *mu, double *xi, double *loc)
+__device__ __forceinline__ void jdt_cell(int nx, int ny, double ids, double ids2, const Model &M, const double *u,
+                                         const double *mu, int i, int j, double &xi, double &loc)
 {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63), j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= nx || j >= ny) return;
     const Cell c = cell_glob<P32>(u, nx, ny, i, j, M, ids2);
     const double mc = mu[(size_t)j * nx + i];
     double lo = 0.0, x = 0.0;
@@ -495,27 +493,46 @@ __global__ void __launch_bounds__(256) k_jdt_xi(int nx, int ny, double ids, doub
         lo += om * (c.f0p * Lam + c.f1p * Gam + (cIsR ? B * ids : -B * ids));
         x += (cIsR ? om * A : -om * A) * ids;
     }
-    xi[(size_t)j * nx + i] = x;
-    loc[(size_t)j * nx + i] = lo;
+    xi = x;
+    loc = lo;
 }
 
-// out = a lam + b mu + g (local + L(xi))
-__global__ void __launch_bounds__(256) k_jdt_out(int nx, int ny, double ids2, const double *xi, const double *loc,
-                                                 const double *lam, const double *mu, double a, double b, double g,
-                                                 double *out, unsigned long long *clr)
+// out = a lam + b mu + g J_D(u)^T mu in one kernel: a workgroup owns a JT_X x JT_Y tile,
+// forms xi on the tile and its one-cell ring (ghost positions take the reflected cell's
+// value) and local on the tile in LDS, then applies the Laplacian to xi from LDS.
+// clr (nullable): two reduction words zeroed for a later kernel of the stream.
+constexpr int JT_X = 64, JT_Y = 16;
+template <bool P32>
+__global__ void __launch_bounds__(256) k_jdt(int nx, int ny, double ids, double ids2, Model M, const double *u,
+                                             const double *mu, const double *lam, double a, double b, double g,
+                                             double *out, unsigned long long *clr)
 {
-    // clr (nullable): two reduction words zeroed for a later kernel of the stream
+    constexpr int RX = JT_X + 2, RY = JT_Y + 2;
+    __shared__ double sxi[RY * RX], sloc[RY * RX];
     if (clr != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) clr[threadIdx.x] = 0ull;
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63), j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= nx || j >= ny) return;
-    const size_t o = (size_t)j * nx + i;
-    const int im = crefl(i - 1, nx), ip = crefl(i + 1, nx), jm = crefl(j - 1, ny), jp = crefl(j + 1, ny);
-    const double lx = (xi[(size_t)j * nx + ip] + xi[(size_t)j * nx + im] + xi[(size_t)jp * nx + i]
-                       + xi[(size_t)jm * nx + i] - 4.0 * xi[o]) * ids2;
-    double v = g * (loc[o] + lx);
-    if (b != 0.0) v += b * mu[o];
-    if (a != 0.0) v += a * lam[o];
-    out[o] = v;
+    const int i0 = blockIdx.x * JT_X, j0 = blockIdx.y * JT_Y;
+    for (int e = threadIdx.x; e < RX * RY; e += 256) {
+        const int li = e % RX, lj = e / RX;
+        const int ri = i0 - 1 + li, rj = j0 - 1 + lj; // -1 and nx / ny are the ghost layer
+        if (ri > nx || rj > ny) continue;             // beyond it: never read
+        double x, l;
+        jdt_cell<P32>(nx, ny, ids, ids2, M, u, mu, crefl(ri, nx), crefl(rj, ny), x, l);
+        sxi[e] = x;
+        sloc[e] = l;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < JT_X * JT_Y; e += 256) {
+        const int ti = e % JT_X, tj = e / JT_X;
+        const int i = i0 + ti, j = j0 + tj;
+        if (i >= nx || j >= ny) continue;
+        const int c = (tj + 1) * RX + ti + 1;
+        const double lx = (sxi[c + 1] + sxi[c - 1] + sxi[c + RX] + sxi[c - RX] - 4.0 * sxi[c]) * ids2;
+        const size_t o = (size_t)j * nx + i;
+        double v = g * (sloc[c] + lx);
+        if (b != 0.0) v += b * mu[o];
+        if (a != 0.0) v += a * lam[o];
+        out[o] = v;
+    }
 }
 
 // out[i][j] = in[j][i] through a 64x64 LDS tile
@@ -752,7 +769,7 @@ tf_status sb_solve(Choice ch, bool trans, int mode, int nl, int np, const double
 struct AdjBuffers {
     int nx = 0, ny = 0;
     double *bx = nullptr, *by = nullptr, *mu = nullptr, *r = nullptr, *rT = nullptr, *y = nullptr, *yT = nullptr;
-    double *xi = nullptr, *loc = nullptr, *dk1 = nullptr, *dk0 = nullptr, *work = nullptr, *part = nullptr;
+    double *dk1 = nullptr, *dk0 = nullptr, *work = nullptr, *part = nullptr;
     double *hpart = nullptr;
     unsigned long long *red = nullptr, *hred = nullptr;
 };
@@ -762,7 +779,7 @@ std::map<const tf_grid *, AdjBuffers> g_adj;
 
 void free_adj(AdjBuffers &b)
 {
-    double *ps[] = {b.bx, b.by, b.mu, b.r, b.rT, b.y, b.yT, b.xi, b.loc, b.dk1, b.dk0, b.work, b.part};
+    double *ps[] = {b.bx, b.by, b.mu, b.r, b.rT, b.y, b.yT, b.dk1, b.dk0, b.work, b.part};
     for (double *p : ps) (void)hipFree(p);
     (void)hipFree(b.red);
     if (b.hpart) (void)hipHostFree(b.hpart);
@@ -783,8 +800,7 @@ tf_status get_adj(const tf_grid *g, int nx, int ny, AdjBuffers **out)
     bool ok = hipMalloc(&b.bx, 5 * N * sizeof(double)) == hipSuccess && hipMalloc(&b.by, 5 * N * sizeof(double)) == hipSuccess
               && hipMalloc(&b.mu, N * sizeof(double)) == hipSuccess && hipMalloc(&b.r, N * sizeof(double)) == hipSuccess
               && hipMalloc(&b.rT, N * sizeof(double)) == hipSuccess && hipMalloc(&b.y, N * sizeof(double)) == hipSuccess
-              && hipMalloc(&b.yT, N * sizeof(double)) == hipSuccess && hipMalloc(&b.xi, N * sizeof(double)) == hipSuccess
-              && hipMalloc(&b.loc, N * sizeof(double)) == hipSuccess && hipMalloc(&b.dk1, N * sizeof(double)) == hipSuccess
+              && hipMalloc(&b.yT, N * sizeof(double)) == hipSuccess && hipMalloc(&b.dk1, N * sizeof(double)) == hipSuccess
               && hipMalloc(&b.dk0, N * sizeof(double)) == hipSuccess
               && hipMalloc(&b.work, 3 * N * sizeof(double)) == hipSuccess
               && hipMalloc(&b.part, 2 * 4096 * sizeof(double)) == hipSuccess
@@ -803,14 +819,12 @@ tf_status get_adj(const tf_grid *g, int nx, int ny, AdjBuffers **out)
 }
 
 tf_status jdt(const tf_detail::GridView &v, const double *u, const double *mu, const double *lam, double a, double b,
-              double gmul, double *out, AdjBuffers &B, unsigned long long *clr = nullptr)
+              double gmul, double *out, unsigned long long *clr = nullptr)
 {
     const double ids = 1.0 / v.ds, ids2 = ids * ids;
-    const dim3 grid((v.nx + 63) / 64, (v.ny + 3) / 4), blk(256);
-    if (v.M.p32) tf::k_jdt_xi<true><<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids, ids2, v.M, u, mu, B.xi, B.loc);
-    else tf::k_jdt_xi<false><<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids, ids2, v.M, u, mu, B.xi, B.loc);
-    TF_AHIP(hipGetLastError());
-    tf::k_jdt_out<<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids2, B.xi, B.loc, lam, mu, a, b, gmul, out, clr);
+    const dim3 grid((v.nx + tf::JT_X - 1) / tf::JT_X, (v.ny + tf::JT_Y - 1) / tf::JT_Y), blk(256);
+    if (v.M.p32) tf::k_jdt<true><<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids, ids2, v.M, u, mu, lam, a, b, gmul, out, clr);
+    else tf::k_jdt<false><<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids, ids2, v.M, u, mu, lam, a, b, gmul, out, clr);
     TF_AHIP(hipGetLastError());
     return TF_OK;
 }
@@ -970,7 +984,7 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
     for (it = 1; it <= max_iter; ++it) {
         // r = lambda - (I + c J^T) mu
         // (the reduction words of this iteration's y solve are zeroed by the same kernel)
-        if ((st = jdt(v, h_np1, B.mu, lambda_inout, 1.0, -1.0, -c, B.r, B, B.red)) != TF_OK) return st;
+        if ((st = jdt(v, h_np1, B.mu, lambda_inout, 1.0, -1.0, -c, B.r, B.red)) != TF_OK) return st;
         // (I + c J_x)^-T: rows as lines; the whole-row kernel and the partitioned solver
         // read r and write y row by row, the other variants work on the transposed layout
         if (rowx) {
@@ -1018,7 +1032,7 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
     }
     // lambda^n = mu - (1 - theta) dt J_D(u^n)^T mu
     if (v.theta < 1.0) {
-        if ((st = jdt(v, h_n, B.mu, nullptr, 0.0, 1.0, -(1.0 - v.theta) * dt, lambda_inout, B)) != TF_OK) return st;
+        if ((st = jdt(v, h_n, B.mu, nullptr, 0.0, 1.0, -(1.0 - v.theta) * dt, lambda_inout)) != TF_OK) return st;
     } else {
         TF_AHIP(hipMemcpyAsync(lambda_inout, B.mu, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
@@ -1032,10 +1046,8 @@ tf_status tf_jacobian_apply_t(tf_grid *g, const double *u, const double *mu, dou
     tf_detail::GridView v;
     if (g == nullptr || u == nullptr || mu == nullptr || out == nullptr) return afail(TF_EINVAL, "NULL argument");
     if (!tf_detail::grid_view(g, &v)) return afail(TF_ESTATE, "model not set");
-    AdjBuffers *Bp;
-    tf_status st = get_adj(g, v.nx, v.ny, &Bp);
-    if (st != TF_OK) return st;
-    if ((st = jdt(v, u, mu, nullptr, 0.0, 0.0, 1.0, out, *Bp)) != TF_OK) return st;
+    tf_status st;
+    if ((st = jdt(v, u, mu, nullptr, 0.0, 0.0, 1.0, out)) != TF_OK) return st;
     TF_AHIP(hipStreamSynchronize(v.stream));
     return TF_OK;
 }
