@@ -245,6 +245,37 @@ def test_rollout_on_a_side_stream_matches_default_stream():
         assert torch.equal(a, r)
 
 
+@pytest.fixture(scope="module")
+def adjoint512_step(orc):
+    """u^n (the seed-4 film of the 512^2 adjoint workload), the oracle's u^{n+1} after one
+    backward-Euler step of dt = 0.1, a random lambda^{n+1} and the oracle's adjoint step."""
+    cfg = synth.CONFIGS["adjoint512"]
+    un = synth.noise_film(cfg.n, cfg.n, cfg.seed, 1.0, 0.01)
+    M = orc.Model()
+    unp1, res = orc.step(M, orc.Scheme(tol=1e-13), un, cfg.ds, cfg.dt)
+    assert res.status == orc.OK
+    lam = np.random.default_rng(21).standard_normal((cfg.n, cfg.n))
+    ref, gk_ref, _ = orc.adjoint_step(M, un, unp1, lam, cfg.ds, cfg.dt, 1.0, tol=1e-13)
+    return un, unp1, lam, ref, gk_ref
+
+
+@pytest.mark.parametrize("xsweep", ["row", "partitioned"])
+def test_512_adjoint_step_matches_oracle(adjoint512_step, xsweep):
+    """One adjoint step at the full size of the 512^2 adjoint workload (L = 16 lambda_m),
+    on the solver variants its timed run uses (whole-row transposed row solves and the tuned
+    column solves) and on the partitioned ones: lambda^n and the dL/dkappa contribution
+    against the oracle's adjoint step from the same u^n, u^{n+1} and lambda^{n+1}."""
+    un, unp1, lam, ref, gk_ref = adjoint512_step
+    cfg = synth.CONFIGS["adjoint512"]
+    n, ds, dt = cfg.n, cfg.ds, cfg.dt
+    g = grid(n, n, ds)
+    g.set_xsweep(xsweep)
+    lg = gpu(lam)
+    gk, _ = g.adjoint_step(gpu(un), gpu(unp1), dt, lg, tol=1e-13)
+    assert np.max(np.abs(lg.cpu().numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
+    assert gk == pytest.approx(gk_ref, rel=1e-9)
+
+
 def test_full_size_rollout_gradient_matches_finite_differences():
     """The 512^2 adjoint workload as timed (L = 16 lambda_m, 400 backward-Euler steps of dt = 0.1,
     checkpoints every 20, p0 = 0 on the seed-4 film, target = the seed-5 film run forward over the
