@@ -261,10 +261,12 @@ tf_status tf_jacobian_apply_t(tf_grid *g, const double *u, const double *mu, dou
  * entries, in increasing q): q_out[p], s_out[p] (group mean) and count_out[p] (group size;
  * nullable) for every nonempty group with 0 < q_r <= qmax; *npoints (host) receives the
  * number of groups. TF_EINVAL when capacity is too small (npoints then holds the number
- * needed) or qmax spans more than 2^26 groups. Work is enqueued on `stream` (hipStream_t,
- * NULL = default) and the call returns after it has finished. The FFT plan and device scratch
- * (8 n (n + 2) bytes plus the smoothing window and group sums) are kept per (device, n) for
- * later calls until tf_spectrum_release; calls are serialised by a lock. */
+ * needed) or qmax spans more than 2^26 groups. Each group's sum is formed in a fixed order, so
+ * the output is bit-reproducible. Work is enqueued on `stream` (hipStream_t, NULL = default)
+ * and the call returns after it has finished. The FFT plan and device scratch (8 n (n + 2)
+ * bytes plus the smoothing window, the group sums and an index of the window by group, about
+ * 4 pi M bytes) are kept per (device, n) for later calls until tf_spectrum_release; calls are
+ * serialised by a lock. */
 tf_status tf_radial_spectrum(const double *h, int n, double ds, double h0, double sigma, double qmax, void *stream,
                              double *q_out, double *s_out, int *count_out, int capacity, int *npoints);
 /* Frees the plans and scratch kept by tf_radial_spectrum on every device (waits for each

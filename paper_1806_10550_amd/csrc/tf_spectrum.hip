@@ -6,8 +6,9 @@
 // gathered into a window of the wavenumber plane that covers the disk
 // |k|^2 <= M plus the Gaussian's reach (indices taken modulo n, so the smoothing is the
 // periodic convolution over the whole plane); two separable passes smooth the window; one
-// thread per wavevector of the disk adds its smoothed value into the sum of its group
-// m = kx^2 + ky^2 (all wavevectors of a group have the same |q|). Only the FFT touches all
+// thread per group m = kx^2 + ky^2 (all wavevectors of a group have the same |q|) sums its
+// smoothed values in a fixed order (an index of the window by group, built once per
+// window on the host), so spectra are bit-reproducible. Only the FFT touches all
 // n^2 values; the window holds (2 sqrt(M) + 2 r + 1)^2 values.
 //
 // Host part (steps 5-7): the fit has about N/10 unknowns, the smoothed curve 400 points: a
@@ -77,22 +78,21 @@ __global__ void __launch_bounds__(256) k_spec_smooth(const double *__restrict__ 
     out[t] = s;
 }
 
-// Group sums over the disk: S is the smoothed window of side 2R+1 centred on k = 0.
-__global__ void __launch_bounds__(256) k_spec_radial(const double *__restrict__ S, int R, int n, long long M,
+// Group sums over the disk: S is the smoothed window of side 2R+1 centred on k = 0. One
+// thread per group m = kx^2 + ky^2 (0 <= m <= M) adds its wavevectors' values in the
+// order of the index (window positions sorted by group, then by position), so the sums
+// do not depend on scheduling.
+__global__ void __launch_bounds__(256) k_spec_groups(const double *__restrict__ S, const int *__restrict__ perm,
+                                                     const long long *__restrict__ off, long long M,
                                                      double *__restrict__ sum, int *__restrict__ cnt)
 {
-    const int W = 2 * R + 1;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= W * W) return;
-    const int kx = t % W - R, ky = t / W - R;
-    // each wavevector of the n x n spectrum once: kx, ky in [-n/2, n/2 - 1] (n even) or
-    // [-(n-1)/2, (n-1)/2] (n odd)
-    const int lo = -(n / 2), hi = (n - 1) / 2;
-    if (kx < lo || kx > hi || ky < lo || ky > hi) return;
-    const long long m = (long long)kx * kx + (long long)ky * ky;
+    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (m > M) return;
-    atomicAdd(&sum[m], S[t]);
-    atomicAdd(&cnt[m], 1);
+    const long long b = off[m], e = off[m + 1];
+    double acc = 0.0;
+    for (long long i = b; i < e; ++i) acc += S[perm[i]];
+    sum[m] = acc;
+    cnt[m] = (int)(e - b);
 }
 
 } // namespace tf
@@ -115,6 +115,12 @@ struct SpecWork {
     double *small = nullptr; // A | B | C | weights | sums, doubles
     int *cnt = nullptr;
     size_t small_cap = 0, cnt_cap = 0;
+    // index of the window by group for the last (M, R): perm lists window positions sorted
+    // by m = kx^2 + ky^2 (then by position), group m owns perm[off[m] .. off[m+1])
+    int *perm = nullptr;
+    long long *off = nullptr;
+    long long idx_M = -1;
+    int idx_R = -1;
 };
 struct WorkKey {
     int device, n;
@@ -129,7 +135,56 @@ void free_work(SpecWork &w)
     if (w.buf) (void)hipFree(w.buf);
     if (w.small) (void)hipFree(w.small);
     if (w.cnt) (void)hipFree(w.cnt);
+    if (w.perm) (void)hipFree(w.perm);
+    if (w.off) (void)hipFree(w.off);
     w = SpecWork{};
+}
+
+// The window index for groups 0..M over a window of half side R (n x n spectrum), built on
+// the host by a counting sort over m (positions in increasing order within a group) and kept
+// until the next call with another (M, R). Called with g_spec_mu held.
+tf_status get_index(SpecWork &w, int n, int R, long long M)
+{
+    if (w.idx_M == M && w.idx_R == R) return TF_OK;
+    const int Wr = 2 * R + 1;
+    const int lo = -(n / 2), hi = (n - 1) / 2;
+    const long long npos = (long long)Wr * Wr;
+    std::vector<long long> off(M + 2, 0);
+    auto group = [&](long long t) -> long long {
+        const int kx = (int)(t % Wr) - R, ky = (int)(t / Wr) - R;
+        if (kx < lo || kx > hi || ky < lo || ky > hi) return -1;
+        const long long m = (long long)kx * kx + (long long)ky * ky;
+        return m <= M ? m : -1;
+    };
+    for (long long t = 0; t < npos; ++t) {
+        const long long m = group(t);
+        if (m >= 0) ++off[m + 1];
+    }
+    for (long long m = 0; m <= M; ++m) off[m + 1] += off[m];
+    std::vector<int> perm((size_t)off[M + 1]);
+    std::vector<long long> next(off.begin(), off.end() - 1);
+    for (long long t = 0; t < npos; ++t) {
+        const long long m = group(t);
+        if (m >= 0) perm[(size_t)next[m]++] = (int)t;
+    }
+    if (w.perm) (void)hipFree(w.perm);
+    if (w.off) (void)hipFree(w.off);
+    w.perm = nullptr;
+    w.off = nullptr;
+    w.idx_M = -1;
+    if (hipMalloc(&w.perm, std::max<size_t>(perm.size(), 1) * sizeof(int)) != hipSuccess
+        || hipMalloc(&w.off, off.size() * sizeof(long long)) != hipSuccess) {
+        if (w.perm) (void)hipFree(w.perm);
+        w.perm = nullptr;
+        w.off = nullptr;
+        return sfail(TF_ENOMEM, "spectrum index allocation failed");
+    }
+    if (hipMemcpy(w.perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess
+        || hipMemcpy(w.off, off.data(), off.size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess)
+        return sfail(TF_EDEVICE, "spectrum index upload failed");
+    w.idx_M = M;
+    w.idx_R = R;
+    return TF_OK;
 }
 
 // Called with g_spec_mu held.
@@ -216,6 +271,7 @@ tf_status tf_radial_spectrum(const double *h, int n, double ds, double h0, doubl
     SpecWork *wk;
     tf_status st = get_work(n, small, (size_t)(M + 1), &wk);
     if (st != TF_OK) return st;
+    if ((st = get_index(*wk, n, R, M)) != TF_OK) return st;
     StreamDrain drain{s};
     double *A = wk->small + oA, *B = wk->small + oB, *C = wk->small + oC, *wd = wk->small + oW,
            *sum = wk->small + oS;
@@ -225,15 +281,13 @@ tf_status tf_radial_spectrum(const double *h, int n, double ds, double h0, doubl
     auto *F = (hipfftDoubleComplex *)wk->buf;
     if (hipfftSetStream(wk->plan, s) != HIPFFT_SUCCESS || hipfftExecD2Z(wk->plan, wk->buf, F) != HIPFFT_SUCCESS)
         return sfail(TF_EDEVICE, "hipfftExecD2Z failed");
-    if (hipMemcpyAsync(wd, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess
-        || hipMemsetAsync(sum, 0, (size_t)(M + 1) * sizeof(double), s) != hipSuccess
-        || hipMemsetAsync(wk->cnt, 0, (size_t)(M + 1) * sizeof(int), s) != hipSuccess)
+    if (hipMemcpyAsync(wd, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
         return sfail(TF_EDEVICE, "spectrum scratch setup failed");
     const double inv_n2 = 1.0 / ((double)n * (double)n);
     tf::k_spec_window<<<(W * W + 255) / 256, 256, 0, s>>>(F, n, E, inv_n2, A);
     tf::k_spec_smooth<0><<<(Wr * W + 255) / 256, 256, 0, s>>>(A, W, W, wd, r, B);
     tf::k_spec_smooth<1><<<(Wr * Wr + 255) / 256, 256, 0, s>>>(B, Wr, W, wd, r, C);
-    tf::k_spec_radial<<<(Wr * Wr + 255) / 256, 256, 0, s>>>(C, R, n, M, sum, wk->cnt);
+    tf::k_spec_groups<<<(unsigned)((M + 1 + 255) / 256), 256, 0, s>>>(C, wk->perm, wk->off, M, sum, wk->cnt);
     if (hipGetLastError() != hipSuccess) return sfail(TF_EDEVICE, "spectrum kernel launch failed");
     std::vector<double> hs(M + 1);
     std::vector<int> hc(M + 1);
