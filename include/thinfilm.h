@@ -161,6 +161,11 @@ tf_status tf_step(tf_grid *g, double *dt_inout, tf_step_info *info);
 /* nsteps accepted steps; log (host, nsteps entries) may be NULL. Stops at the first
  * failure, leaving h at the last accepted state. */
 tf_status tf_advance(tf_grid *g, int nsteps, double *dt_inout, tf_step_info *log);
+/* tf_advance that also keeps every accepted state: after step s (0-based) the state is
+ * copied into states[s] (host array of nsteps device pointers, each to nx*ny doubles on the
+ * grid's device, disjoint from the bound state and from each other) on the grid's stream;
+ * for the recomputation of a stretch of steps before its adjoint (tf_adjoint_steps). */
+tf_status tf_advance_keep(tf_grid *g, int nsteps, double *dt_inout, double *const *states, tf_step_info *log);
 
 /* Compensated sum of h and its minimum (Sec. "Conservation of Mass"); host outputs. */
 tf_status tf_mass(tf_grid *g, double *mass, double *hmin);
@@ -246,6 +251,14 @@ tf_status tf_ensemble_film_info(const tf_ensemble *e, int film, tf_step_info *in
  * iters_out (host, nullable): Richardson iterations used. */
 tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, double dt, double *lambda_inout,
                           double *dL_dkappa_accum, double tol, int max_iter, int *iters_out);
+/* The adjoint steps of one stretch of nsteps fixed-dt steps in one call: states (host array
+ * of nsteps + 1 device pointers) holds u at the stretch's time levels, states[0] the oldest;
+ * tf_adjoint_step runs for n = nsteps-1 down to 0 with h_n = states[n], h_np1 = states[n+1],
+ * taking lambda_inout from lambda^{nsteps} to lambda^0 and adding every step's dL/dkappa
+ * contribution to *dL_dkappa_accum. iters_out: Richardson iterations of all steps. Stops at the
+ * first failing step and returns its status. */
+tf_status tf_adjoint_steps(tf_grid *g, int nsteps, const double *const *states, double dt, double *lambda_inout,
+                           double *dL_dkappa_accum, double tol, int max_iter, int *iters_out);
 /* out = J_D(u)^T mu with the full analytic Jacobian of the flux-difference operator D
  * (device arrays, nx*ny each). */
 tf_status tf_jacobian_apply_t(tf_grid *g, const double *u, const double *mu, double *out);

@@ -83,19 +83,20 @@ class Rollout(torch.autograd.Function):
         work = torch.empty_like(lam)
         g.bind(work)
         nseg = len(ctx.ckpts)
+        # each segment: recompute its states from the checkpoint in one call, then its adjoint
+        # steps (newest first) in another
+        states = torch.empty((K + 1,) + tuple(lam.shape), dtype=lam.dtype, device=lam.device)
         for seg in range(nseg - 1, -1, -1):
             start = seg * K
             end = min(nsteps, start + K)
+            m = end - start
             work.copy_(ctx.ckpts[seg])
-            states = [work.clone()]
-            for _ in range(start, end):
-                g.step(dt)
-                states.append(work.clone())
-            for s in range(end - start - 1, -1, -1):
-                c, it = g.adjoint_step(states[s], states[s + 1], dt, lam, tol=adj_tol, dkappa=power)
-                gk += c if power else 0.0
-                steps += 1
-                iters += it
+            states[0].copy_(ctx.ckpts[seg])
+            g.advance_keep(m, dt, states[1:m + 1])
+            c, it = g.adjoint_steps(states[:m + 1], dt, lam, tol=adj_tol, dkappa=power)
+            gk += c if power else 0.0
+            steps += m
+            iters += it
         Rollout.stats = {"adjoint_steps": steps, "richardson_iters": iters}
         grad_k = (torch.full(ctx.kappa_shape, gk, dtype=torch.float64, device=lam.device) if power else None)
         return (lam, grad_k) + (None,) * 13

@@ -1041,6 +1041,22 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
     return TF_OK;
 }
 
+tf_status tf_adjoint_steps(tf_grid *g, int nsteps, const double *const *states, double dt, double *lambda_inout,
+                           double *dL_dkappa_accum, double tol, int max_iter, int *iters_out)
+{
+    if (g == nullptr || nsteps < 0 || (nsteps > 0 && states == nullptr) || lambda_inout == nullptr)
+        return afail(TF_EINVAL, "bad argument");
+    int total = 0;
+    tf_status st = TF_OK;
+    for (int s = nsteps - 1; s >= 0 && st == TF_OK; --s) {
+        int it = 0;
+        st = tf_adjoint_step(g, states[s], states[s + 1], dt, lambda_inout, dL_dkappa_accum, tol, max_iter, &it);
+        total += it;
+    }
+    if (iters_out) *iters_out = total;
+    return st;
+}
+
 tf_status tf_jacobian_apply_t(tf_grid *g, const double *u, const double *mu, double *out)
 {
     tf_detail::GridView v;

@@ -679,6 +679,26 @@ tf_status tf_advance(tf_grid *g, int nsteps, double *dt_inout, tf_step_info *log
     return st != TF_OK ? st : cb;
 }
 
+tf_status tf_advance_keep(tf_grid *g, int nsteps, double *dt_inout, double *const *states, tf_step_info *log)
+{
+    if (g == nullptr || dt_inout == nullptr || nsteps < 0 || (nsteps > 0 && states == nullptr))
+        return fail(TF_EINVAL, "bad argument");
+    for (int s = 0; s < nsteps; ++s)
+        if (states[s] == nullptr) return fail(TF_EINVAL, "NULL state buffer");
+    tf_status st = ensure_ready(g);
+    if (st != TF_OK) return st;
+    const size_t bytes = (size_t)g->nx * g->ny * sizeof(double);
+    for (int s = 0; s < nsteps && st == TF_OK; ++s) {
+        st = do_step(g, dt_inout, log ? &log[s] : nullptr);
+        if (st == TF_OK) {
+            const hipError_t e = hipMemcpyAsync(states[s], g->cur, bytes, hipMemcpyDeviceToDevice, g->stream);
+            if (e != hipSuccess) st = fail(TF_EDEVICE, std::string("state copy: ") + hipGetErrorString(e));
+        }
+    }
+    const tf_status cb = copy_back(g);
+    return st != TF_OK ? st : cb;
+}
+
 tf_status tf_mass(tf_grid *g, double *mass, double *hmin)
 {
     if (g == nullptr || mass == nullptr || hmin == nullptr) return fail(TF_EINVAL, "NULL argument");

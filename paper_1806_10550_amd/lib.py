@@ -103,6 +103,8 @@ def lib():
         L.tf_ensemble_film_info.argtypes = [P, C.c_int, C.POINTER(StepInfo)]
         L.tf_adjoint_step.argtypes = [P, P, P, D, P, DP, D, C.c_int, IP]
         L.tf_jacobian_apply_t.argtypes = [P, P, P, P]
+        L.tf_adjoint_steps.argtypes = [P, C.c_int, P, D, P, DP, D, C.c_int, IP]
+        L.tf_advance_keep.argtypes = [P, C.c_int, C.POINTER(D), P, P]
         L.tf_penta_solve.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, C.c_int, P]
         L.tf_penta_solve_noalloc.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, C.c_int, P]
         L.tf_autotune.argtypes = [C.c_int, C.c_int, C.c_int, C.c_char_p]
@@ -314,6 +316,33 @@ class Grid:
         it = C.c_int(0)
         _check(lib().tf_adjoint_step(self._h, _ptr(h_n), _ptr(h_np1), float(dt), _ptr(lam),
                                      C.byref(g) if dkappa else None, float(tol), int(max_iter), C.byref(it)))
+        return (g.value if dkappa else None), it.value
+
+    def advance_keep(self, nsteps: int, dt: float, states):
+        """advance(nsteps, dt) keeping every accepted state: states[s] (a (>= nsteps, ny, nx)
+        float64 CUDA tensor) receives the state after step s + 1 (tf_advance_keep)."""
+        _ptr(states)
+        if states.dim() != 3 or states.shape[0] < nsteps or tuple(states.shape[1:]) != (self.ny, self.nx):
+            raise ValueError(f"states must be a (>= {nsteps}, {self.ny}, {self.nx}) tensor")
+        ptrs = (C.c_void_p * max(nsteps, 1))(*[states[s].data_ptr() for s in range(nsteps)])
+        d = C.c_double(dt)
+        _check(lib().tf_advance_keep(self._h, int(nsteps), C.byref(d), ptrs, None))
+        return d.value
+
+    def adjoint_steps(self, states, dt: float, lam, tol: float = 1e-13, max_iter: int = 2000, dkappa: bool = True):
+        """Adjoint steps of a stretch: states (a contiguous (nsteps + 1, ny, nx) tensor, oldest
+        first); lam goes from lambda^{nsteps} to lambda^0 (tf_adjoint_steps). Returns (summed
+        dL/dkappa contribution or None, Richardson iterations)."""
+        _ptr(states)
+        self._fields(lam)
+        if states.dim() != 3 or states.shape[0] < 1 or tuple(states.shape[1:]) != (self.ny, self.nx):
+            raise ValueError(f"states must be a (nsteps + 1, {self.ny}, {self.nx}) tensor")
+        n = states.shape[0] - 1
+        ptrs = (C.c_void_p * max(n + 1, 1))(*[states[s].data_ptr() for s in range(n + 1)])
+        g = C.c_double(0.0)
+        it = C.c_int(0)
+        _check(lib().tf_adjoint_steps(self._h, int(n), ptrs, float(dt), _ptr(lam), C.byref(g) if dkappa else None,
+                                      float(tol), int(max_iter), C.byref(it)))
         return (g.value if dkappa else None), it.value
 
     def jacobian_apply_t(self, u, mu, out):

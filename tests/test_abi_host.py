@@ -29,6 +29,9 @@ def L():
     lib.tf_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     lib.tf_adjoint_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
                                     C.c_double, C.c_int, C.c_void_p]
+    lib.tf_adjoint_steps.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                     C.c_double, C.c_int, C.c_void_p]
+    lib.tf_advance_keep.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     return lib
 
 
@@ -57,6 +60,8 @@ def test_null_handles(L):
     assert L.tf_set_model(None, 10.0, 0.1, 3.0, 2.0) == TF_EINVAL
     assert L.tf_step(None, None, None) == TF_EINVAL
     assert L.tf_adjoint_step(None, None, None, 0.1, None, None, 1e-10, 10, None) == TF_EINVAL
+    assert L.tf_adjoint_steps(None, 1, None, 0.1, None, None, 1e-10, 10, None) == TF_EINVAL
+    assert L.tf_advance_keep(None, 1, None, None, None) == TF_EINVAL
 
 
 def test_penta_solve_validates_before_allocating(L):

@@ -218,6 +218,41 @@ def test_rollout_gradient_matches_oracle_adjoint(orc):
     assert kap.grad.item() == pytest.approx(gk, rel=1e-8)
 
 
+def test_advance_keep_and_adjoint_steps_match_single_steps():
+    """tf_advance_keep keeps exactly the states that single tf_step calls reach, and
+    tf_adjoint_steps over the stretch equals tf_adjoint_step newest first (lambda bit for bit,
+    the summed dL/dkappa to rounding)."""
+    n, steps, dt = 48, 7, 0.1
+    ds = 16 * synth.lambda_m(10.0) / 512
+    b = gpu(synth.noise_film(n, n, seed=4, amp=0.01))
+    g = grid(n, n, ds, tol=1e-12)
+    h = b.clone()
+    g.bind(h)
+    ref = [h.clone()]
+    for _ in range(steps):
+        g.step(dt)
+        ref.append(h.clone())
+    states = torch.empty((steps + 1, n, n), dtype=torch.float64, device=DEV)
+    states[0].copy_(b)
+    h2 = b.clone()
+    g.bind(h2)
+    g.advance_keep(steps, dt, states[1:])
+    for s in range(steps + 1):
+        assert torch.equal(states[s], ref[s]), s
+    assert torch.equal(h2, ref[-1])
+    lam0 = gpu(np.random.default_rng(9).standard_normal((n, n)))
+    lam1 = lam0.clone()
+    gk1, it1 = 0.0, 0
+    for s in range(steps - 1, -1, -1):
+        c, it = g.adjoint_step(ref[s], ref[s + 1], dt, lam1, tol=1e-12)
+        gk1 += c
+        it1 += it
+    lam2 = lam0.clone()
+    gk2, it2 = g.adjoint_steps(states, dt, lam2, tol=1e-12)
+    assert torch.equal(lam1, lam2) and it1 == it2
+    assert gk2 == pytest.approx(gk1, rel=1e-13, abs=1e-300)
+
+
 def test_rollout_on_a_side_stream_matches_default_stream():
     """A rollout run under another torch stream uses a grid bound to that stream (the grid
     cache is keyed by stream), so its checkpoint copies and the library's launches stay in
