@@ -128,14 +128,6 @@ struct Cell {
     double u, lap, f0, f1, f0p, f1p; // f0p, f1p hold f0'/2 and f1'/2
 };
 
-// Even reflection across the boundary faces (no-flux ghosts), clamped so that a
-// ragged tile never reads outside the grid.
-__device__ __forceinline__ int crefl(int k, int n)
-{
-    if (k < 0) k = -1 - k;
-    if (k >= n) k = 2 * n - 1 - k;
-    return k < 0 ? 0 : (k >= n ? n - 1 : k);
-}
 
 // LDS u tile: (line l, position p) in tile-local coordinates, -HALO <= l, p < TILE+HALO.
 // DIR 0 (y sweep): lines are grid columns (x), positions rows (y).
@@ -166,14 +158,6 @@ __device__ __forceinline__ Cell cell_at(const double *sU, const Model &M, double
     return c;
 }
 
-// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous run
-// of tiles so that neighbouring tiles share halos in the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int n)
-{
-    const int q = n >> 3, r = n & 7;
-    const int x = b & 7, k = b >> 3;
-    return x * q + (x < r ? x : r) + k;
-}
 
 // ---- 2x2 / 2x5 helpers for the interface chain --------------------------------------
 struct M2 { double a, b, c, d; }; // [[a b] [c d]]

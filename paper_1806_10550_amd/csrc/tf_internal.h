@@ -37,6 +37,41 @@ constexpr int XR_MAX_NX = XR_CPL * 64 * XR_WAVES;
 __host__ __device__ constexpr int xr_lds(int waves) { return waves * 2400; }
 constexpr int XR_ROW4_MAX_NX = XR_CPL * 64 * 4;      // rows a 4-wave workgroup holds
 
+// Geometry of the whole-row sweep and of the whole-line solver (host and device).
+// LDS index of position i (>= 0) of a staged row: one padding double every 16, so that
+// lanes reading 16 consecutive cells each (stride 17 doubles) hit distinct banks.
+__host__ __device__ inline int xr_pad(int i) { return i + (i >> 4); }
+
+// Geometry of one launch (host computed, identical for every row of the grid).
+struct XRowGeom {
+    int S;        // sub-segments (lanes) per row
+    int W;        // waves per row
+    int R;        // rows per workgroup
+    int pu, p2;   // LDS doubles per row: staged u row; X row / tree / output staging
+    int waves;    // waves per workgroup (4 or 8)
+};
+
+__host__ __device__ inline int xr_cells_u(int nx) { return xr_pad(nx + 4) + 1; }
+
+// Staging loads per thread: nx + 4 <= 64 W XR_CPL + 4 cells over 64 W threads.
+constexpr int XR_STAGE = XR_CPL + 1;
+
+__host__ __device__ inline XRowGeom xrow_geom(int nx)
+{
+    XRowGeom g{};
+    g.S = (nx + XR_CPL - 1) / XR_CPL;
+    g.W = (g.S + 63) / 64;
+    g.pu = xr_cells_u(nx);
+    const int px = xr_pad(nx + 2) + 1, pt = NREL * g.S, pv = xr_pad(nx) + 1;
+    g.p2 = px > pt ? px : pt;
+    if (pv > g.p2) g.p2 = pv;
+    g.waves = g.W <= 4 ? 4 : XR_WAVES;
+    g.R = g.waves / g.W;
+    if (g.R < 1) g.R = 1;
+    while (g.R > 1 && g.R * (g.pu + g.p2) > xr_lds(g.waves)) --g.R;
+    return g;
+}
+
 // Segments of a line of n >= 2 cells: TILE cells each, except that a last segment of
 // a single cell borrows one from its neighbour (every segment has >= 2 cells).
 __host__ __device__ inline int seg_count(int n) { return (n + TILE - 1) / TILE; }
@@ -47,6 +82,24 @@ __host__ __device__ inline int seg_start(int q, int n)
     int s = q * TILE;
     if (q == P - 1 && P > 1 && n - s < 2) s -= 1;
     return s;
+}
+
+// Even reflection across the boundary faces (no-flux ghosts), clamped so that a
+// ragged tile never reads outside the grid.
+__host__ __device__ __forceinline__ int crefl(int k, int n)
+{
+    if (k < 0) k = -1 - k;
+    if (k >= n) k = 2 * n - 1 - k;
+    return k < 0 ? 0 : (k >= n ? n - 1 : k);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous run
+// of tiles so that neighbouring tiles share halos in the same L2.
+__host__ __device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int q = n >> 3, r = n & 7;
+    const int x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
 }
 
 // Thin-film models (eq. GeneralDisPreForm): f0 = cap h^3, f1 = h^3 Pi'(h).

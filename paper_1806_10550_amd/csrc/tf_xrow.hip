@@ -24,40 +24,6 @@
 
 namespace tf {
 
-// LDS index of position i (>= 0) of a staged row: one padding double every 16, so that
-// lanes reading 16 consecutive cells each (stride 17 doubles) hit distinct banks.
-__host__ __device__ inline int xr_pad(int i) { return i + (i >> 4); }
-
-// Geometry of one launch (host computed, identical for every row of the grid).
-struct XRowGeom {
-    int S;        // sub-segments (lanes) per row
-    int W;        // waves per row
-    int R;        // rows per workgroup
-    int pu, p2;   // LDS doubles per row: staged u row; X row / tree / output staging
-    int waves;    // waves per workgroup (4 or 8)
-};
-
-__host__ __device__ inline int xr_cells_u(int nx) { return xr_pad(nx + 4) + 1; }
-
-// Staging loads per thread: nx + 4 <= 64 W XR_CPL + 4 cells over 64 W threads.
-constexpr int XR_STAGE = XR_CPL + 1;
-
-__host__ __device__ inline XRowGeom xrow_geom(int nx)
-{
-    XRowGeom g{};
-    g.S = (nx + XR_CPL - 1) / XR_CPL;
-    g.W = (g.S + 63) / 64;
-    g.pu = xr_cells_u(nx);
-    const int px = xr_pad(nx + 2) + 1, pt = NREL * g.S, pv = xr_pad(nx) + 1;
-    g.p2 = px > pt ? px : pt;
-    if (pv > g.p2) g.p2 = pv;
-    g.waves = g.W <= 4 ? 4 : XR_WAVES;
-    g.R = g.waves / g.W;
-    if (g.R < 1) g.R = 1;
-    while (g.R > 1 && g.R * (g.pu + g.p2) > xr_lds(g.waves)) --g.R;
-    return g;
-}
-
 bool xrow_supported(int nx)
 {
     if (nx < 4 || nx > XR_MAX_NX) return false;

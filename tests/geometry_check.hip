@@ -1,0 +1,195 @@
+// Host-side bounds check of the kernels' geometry: the segment partition of a line, the
+// sub-segments of a tile, the even reflection of ghost indices, the workgroup -> tile map,
+// the y-sweep column tiles, the LDS layout and staging indices of the tile passes, and the
+// geometry of the whole-row sweep and whole-line solver (lane sub-segments, padding, LDS
+// regions, staging coverage, tree slots). The functions checked are the ones the kernels
+// call (tf_internal.h, host and device); the tile-pass staging loops are restated from
+// stage_tile. Exhaustive over line lengths; prints "geometry check: ok" or the first failure.
+#include "../paper_1806_10550_amd/csrc/tf_internal.h"
+
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+using namespace tf;
+
+static int failures = 0;
+#define CHECK(cond, ...)                                                                    \
+    do {                                                                                    \
+        if (!(cond)) {                                                                      \
+            if (failures++ < 20) {                                                          \
+                std::printf("FAIL %s:%d: %s: ", __FILE__, __LINE__, #cond);                 \
+                std::printf(__VA_ARGS__);                                                   \
+                std::printf("\n");                                                          \
+            }                                                                               \
+        }                                                                                   \
+    } while (0)
+
+// segments of a line and the sub-segments of each tile (tile_body: nsub = min(NSUB, npos/2))
+static void check_segments()
+{
+    for (int n = 2; n <= 20000; ++n) {
+        const int P = seg_count(n);
+        CHECK(seg_start(0, n) == 0 && seg_start(P, n) == n, "n=%d", n);
+        for (int q = 0; q < P; ++q) {
+            const int len = seg_start(q + 1, n) - seg_start(q, n);
+            CHECK(len >= 2 && len <= TILE, "n=%d q=%d len=%d", n, q, len);
+        }
+    }
+    for (int npos = 2; npos <= TILE; ++npos) {
+        const int nsub = npos / 2 < NSUB ? npos / 2 : NSUB;
+        int covered = 0;
+        for (int wave = 0; wave < NSUB; ++wave) {
+            const int ps = (wave * npos) / nsub;
+            const int len = wave < nsub ? ((wave + 1) * npos) / nsub - ps : 0;
+            if (wave < nsub) {
+                CHECK(ps == covered, "npos=%d wave=%d", npos, wave);
+                CHECK(len >= 2 && len <= SUB, "npos=%d wave=%d len=%d", npos, wave, len);
+            }
+            covered += len;
+        }
+        CHECK(covered == npos, "npos=%d covered=%d", npos, covered);
+    }
+}
+
+// ghost indices: the even reflection for one layer beyond each end, clamped beyond that
+static void check_reflection()
+{
+    for (int n = 1; n <= 300; ++n)
+        for (int k = -TILE - 8; k <= n + TILE + 8; ++k) {
+            const int r = crefl(k, n);
+            CHECK(r >= 0 && r < n, "k=%d n=%d r=%d", k, n, r);
+            if (k >= -n && k < 2 * n) {
+                const int e = k < 0 ? -1 - k : (k >= n ? 2 * n - 1 - k : k);
+                CHECK(r == e, "k=%d n=%d r=%d e=%d", k, n, r, e);
+            }
+        }
+}
+
+// workgroup -> tile: a bijection of [0, n) that gives each XCD (b mod 8) a contiguous run
+static void check_xcd_map()
+{
+    for (int n = 1; n <= 5000; ++n) {
+        std::vector<int> seen(n, 0);
+        for (int b = 0; b < n; ++b) {
+            const int t = xcd_tile(b, n);
+            CHECK(t >= 0 && t < n, "b=%d n=%d t=%d", b, n, t);
+            if (t >= 0 && t < n) seen[t]++;
+        }
+        for (int t = 0; t < n; ++t) CHECK(seen[t] == 1, "n=%d tile %d hit %d times", n, t, seen[t]);
+        for (int b = 8; b < n; ++b) CHECK(xcd_tile(b, n) == xcd_tile(b - 8, n) + 1, "n=%d b=%d", n, b);
+    }
+}
+
+// y-sweep tiles own LT0 columns: every grid column exactly once; lanes 0 and 63 carry the
+// neighbouring columns
+static void check_column_tiles()
+{
+    for (int nx = 4; nx <= 5000; ++nx) {
+        const int tiles = (nx + LT0 - 1) / LT0;
+        int covered = 0;
+        for (int tx = 0; tx < tiles; ++tx) {
+            const int x0 = tx * LT0, x1 = x0 + LT0 < nx ? x0 + LT0 : nx;
+            CHECK(x0 == covered && x1 > x0, "nx=%d tx=%d", nx, tx);
+            covered = x1;
+            CHECK(x1 - x0 <= 64 - 2, "nx=%d tx=%d owned=%d", nx, tx, x1 - x0);
+        }
+        CHECK(covered == nx, "nx=%d", nx);
+    }
+}
+
+// LDS indices of the tile staging (stage_tile): u tile rows RU0.. and its extra columns,
+// the second input tile; every index inside its region, every cell the sweeps read staged
+static void check_tile_staging()
+{
+    const int NU = TW * UPITCH, NW = TILE * WPITCH;
+    for (int dir = 0; dir < 2; ++dir) {
+        const int LX0 = dir == 0 ? 1 : 2, RU0 = dir == 0 ? 0 : 1, NRU = dir == 0 ? TW : TW - 2;
+        const int KU = (NRU + NSUB - 1) / NSUB, KB = TILE / NSUB, XPR = dir == 0 ? 2 : 4;
+        const int NX = NRU * XPR, KX = (NX + BLOCK - 1) / BLOCK;
+        std::vector<int> hit(NU, 0);
+        for (int wave = 0; wave < NSUB; ++wave)
+            for (int lane = 0; lane < 64; ++lane) {
+                for (int k = 0; k < KU; ++k) {
+                    const int ly = RU0 + wave + NSUB * k;
+                    if (ly < RU0 + NRU) {
+                        const int i = ly * UPITCH + LX0 + lane;
+                        CHECK(i >= 0 && i < NU, "dir=%d u index %d", dir, i);
+                        if (i >= 0 && i < NU) hit[i]++;
+                    }
+                }
+                for (int k = 0; k < KB; ++k) {
+                    const int i = (wave + NSUB * k) * WPITCH + lane;
+                    CHECK(i >= 0 && i < NW, "dir=%d b index %d", dir, i);
+                }
+                for (int k = 0; k < KX; ++k) {
+                    const int idx = (wave + NSUB * k) * 64 + lane;
+                    if (idx < NX) {
+                        const int ly = RU0 + idx / XPR, q = idx % XPR;
+                        const int lx = dir == 0 ? LX0 + 64 + q : (q < 2 ? q : 64 + q);
+                        const int i = ly * UPITCH + lx;
+                        CHECK(lx < TW && i >= 0 && i < NU, "dir=%d extra index %d", dir, i);
+                        if (i >= 0 && i < NU) hit[i]++;
+                    }
+                }
+            }
+        // the cells the sweeps read: y sweep rows 0..TW-1 x columns 1..TW-2; x sweep rows
+        // 1..TW-2 x columns 0..TW-1; each staged exactly once
+        for (int ly = RU0; ly < RU0 + NRU; ++ly)
+            for (int lx = (dir == 0 ? 1 : 0); lx < (dir == 0 ? TW - 1 : TW); ++lx)
+                CHECK(hit[ly * UPITCH + lx] == 1, "dir=%d cell (%d,%d) staged %d times", dir, ly, lx,
+                      hit[ly * UPITCH + lx]);
+    }
+}
+
+// whole-row sweep / whole-line solver: lanes cover the row (lane 0 may start up to
+// XR_CPL-1 padding positions early), every LDS index inside its region, the staging loop
+// covers the row and its ghosts, and every tree merge and split names two slots of the row
+static void check_rows()
+{
+    for (int nx = 4; nx <= XR_MAX_NX; ++nx) {
+        const XRowGeom g = xrow_geom(nx);
+        CHECK(g.S * XR_CPL >= nx && (g.S - 1) * XR_CPL < nx, "nx=%d S=%d", nx, g.S);
+        CHECK(g.W * 64 >= g.S && g.W <= g.waves && (g.waves == 4 || g.waves == XR_WAVES), "nx=%d", nx);
+        CHECK(g.R >= 1 && g.R * g.W <= g.waves, "nx=%d R=%d W=%d", nx, g.R, g.W);
+        const bool fits = g.R * (g.pu + g.p2) <= xr_lds(g.waves);
+        CHECK(fits, "nx=%d LDS %d > %d", nx, g.R * (g.pu + g.p2), xr_lds(g.waves));
+        const int p0_lane0 = nx - XR_CPL * g.S;
+        CHECK(p0_lane0 <= 0 && p0_lane0 > -XR_CPL, "nx=%d p0=%d", nx, p0_lane0);
+        CHECK(64 * g.W * XR_STAGE >= nx + 4, "nx=%d staging covers %d", nx, 64 * g.W * XR_STAGE);
+        CHECK(xr_pad(nx + 3) < g.pu, "nx=%d u row", nx);                   // staged u row (2 ghosts)
+        CHECK(xr_pad(nx + 1) < g.p2, "nx=%d neighbour rows", nx);          // u(j-1) + u(j+1)
+        CHECK(NREL * g.S <= g.p2, "nx=%d records", nx);                    // record tree
+        CHECK(xr_pad(nx - 1) < g.pu, "nx=%d solution", nx);                // parked factor / v
+        int levels = 0;
+        while ((1 << levels) < g.S) ++levels;
+        for (int l = 1; l <= levels; ++l) {
+            const int half = 1 << (l - 1);
+            const int nm = (g.S - half + 2 * half - 1) / (2 * half);
+            for (int b = 0; b < nm; ++b) {
+                const int a = b * 2 * half, c = a + half;
+                CHECK(a >= 0 && c < g.S, "nx=%d level %d merge %d: slots %d %d", nx, l, b, a, c);
+            }
+            // no pair of neighbouring blocks is left unmerged at this level
+            CHECK(nm * 2 * half + half >= g.S, "nx=%d level %d nm=%d", nx, l, nm);
+        }
+        const int mx = g.waves * 64; // threads of the largest workgroup
+        CHECK(64 * g.W * g.R <= mx, "nx=%d block", nx);
+    }
+}
+
+int main()
+{
+    check_segments();
+    check_reflection();
+    check_xcd_map();
+    check_column_tiles();
+    check_tile_staging();
+    check_rows();
+    if (failures) {
+        std::printf("geometry check: %d failures\n", failures);
+        return 1;
+    }
+    std::printf("geometry check: ok\n");
+    return 0;
+}
