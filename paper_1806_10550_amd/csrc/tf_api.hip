@@ -209,7 +209,7 @@ tf_status enqueue_iteration(tf_grid *g, const double *bnp, const double *uk, dou
     P.out = g->w;
     P.res = res;
     P.res_clear = clr;
-    P.tiles_x = (g->nx + tf::LT0 - 1) / tf::LT0;
+    P.tiles_x = (g->nx + tf::TILE - 1) / tf::TILE;
     P.tiles_y = g->Py;
     if ((st = timed(g, P_REL_Y, [&] { return tf::launch_pass(0, false, P, g->stream); })) != TF_OK) return st;
     tf::ChainParams C{g->nx, g->Py, g->rel, g->chain, g->ext};

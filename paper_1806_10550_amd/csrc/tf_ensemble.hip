@@ -149,7 +149,7 @@ void build_items(tf_ensemble *e, std::vector<int> &items)
     std::vector<int> items_y, items_x, items_cy, items_cx, items_xr;
     for (int f = 0; f < e->nfilms; ++f) {
         const tf::FilmDesc &d = e->desc[f];
-        const int tyx = (d.nx + tf::LT0 - 1) / tf::LT0;
+        const int tyx = (d.nx + tf::TILE - 1) / tf::TILE;
         for (int ty = 0; ty < d.Py; ++ty)
             for (int tx = 0; tx < tyx; ++tx) { items_y.push_back(f); items_y.push_back(tx); items_y.push_back(ty); }
         for (int lb = 0; lb < (d.nx + 63) / 64; ++lb) { items_cy.push_back(f); items_cy.push_back(lb); }
@@ -189,7 +189,7 @@ size_t max_items(const tf_ensemble *e)
 {
     size_t n = 0;
     for (const auto &d : e->desc) {
-        n += 3 * (size_t)d.Py * ((d.nx + tf::LT0 - 1) / tf::LT0) + 2 * (size_t)((d.nx + 63) / 64);
+        n += 3 * (size_t)d.Py * ((d.nx + tf::TILE - 1) / tf::TILE) + 2 * (size_t)((d.nx + 63) / 64);
         n += std::max(3 * (size_t)((d.ny + tf::TILE - 1) / tf::TILE) * d.Px + 2 * (size_t)((d.ny + 63) / 64),
                       tf::xrow_supported(d.nx) ? 2 * (size_t)tf::xrow_blocks(d.nx, d.ny) : 0);
     }

@@ -15,7 +15,6 @@ namespace tf {
 //   one workgroup owns. Inside a tile each of the NSUB waves eliminates a
 //   sub-segment of at most SUB cells for all 64 lines (one line per lane).
 constexpr int TILE = 64;
-constexpr int LT0 = 62;                  // grid columns owned by a y-sweep tile (+2 halo lanes)
 constexpr int NSUB = 4;
 constexpr int SUB = TILE / NSUB;
 constexpr int HALO = 2;

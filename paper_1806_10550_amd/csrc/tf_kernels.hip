@@ -42,8 +42,9 @@ namespace tf {
 // ------------------------------------------------------------------------------------
 // Tile pass. DIR 0: y sweep (columns), DIR 1: x sweep (rows). SOLVE false: emit the
 // tile's segment relations; SOLVE true: finish the solve with the chained boundaries.
-// y-sweep tiles own LT0 = 62 columns: lanes 0 and 63 carry the neighbouring columns so
-// that the x faces of the residual come from lane shuffles.
+// A tile owns 64 lines (one per lane). The x faces of the y sweep's residual come from
+// lane shuffles; the fluxes through the two faces on the tile's x edges are formed once per
+// position before the sweeps and enter the b^n of lanes 0 and 63.
 // ------------------------------------------------------------------------------------
 // Value of the next (lane + 1) / previous (lane - 1) lane of the wave by whole-wave DPP
 // shifts (VALU moves, no LDS permute); the edge lanes get 0 (the sweeps use them only
@@ -84,14 +85,20 @@ __device__ __forceinline__ CellS cell_s(const double *sU, const PassParams &p, i
 // symbolic. FAST: interior tile with 16 positions per wave, no domain boundary inside
 // (no folded ghost columns, no zero-flux faces, no per-lane boundary selects).
 template <int DIR, bool SOLVE, int KM, bool FAST>
-__device__ __forceinline__ void sweep(const double *sU, double *sB, const double *bcol, const PassParams &p,
-                                      int lane, int ps, int len, int pbase, int Np, int gl, int Nl, bool owned, double *fa,
+__device__ __forceinline__ void sweep(const double *sU, double *sB, const double *sCorr, const double *bcol,
+                                      const PassParams &p, int lane, int ps, int len, int pbase, int Np, int gl, int Nl,
+                                      bool owned, double *fa,
                                       double *fb, double *fz, double *fph, double *fps, Rel &mine,
                                       double &rmax, unsigned &flags)
 {
     const double ka = p.ka;
     // x relations pass: w read straight from global memory (each lane walks its row)
     constexpr bool WG = DIR == 1 && !SOLVE;
+    // y relations pass: b^n corrections of this lane (lanes 0 and 63; the others read zeros)
+    const double *corr = sCorr + (lane == 0 ? 0 : (lane == TILE - 1 ? TILE : 2 * TILE));
+    // y sweep: lane 63 takes zero flux through its right face (the tile edge; its b^n carries
+    // the flux there)
+    const bool feok = DIR == 0 && (FAST || gl < Nl - 1) && lane != TILE - 1;
     {
         const CellS cm = cell_s<DIR, KM>(sU, p, lane, ps - 1);
         CellS c0 = cell_s<DIR, KM>(sU, p, lane, ps);
@@ -118,11 +125,12 @@ __device__ __forceinline__ void sweep(const double *sU, double *sB, const double
                     const double eu = lane_next(c0.u), el = lane_next(c0.lap);
                     const double e0 = lane_next(c0.f0), e1 = lane_next(c0.f1);
                     const double Fe0 = __builtin_fma(c0.f0 + e0, el - c0.lap, (c0.f1 + e1) * (eu - c0.u));
-                    const double Fe = (FAST || gl < Nl - 1) ? Fe0 : 0.0;
+                    const double Fe = feok ? Fe0 : 0.0;
                     const double Fwr = lane_prev(Fe);
                     const double Fw = (FAST || gl > 0) ? Fwr : 0.0;
                     const double D = (Fe - Fw) + (fp.F - fm.F);
-                    const double bn = SOLVE ? sB[lp * WPITCH + lane] : bcol[(size_t)gp * p.nx];
+                    // b^n with the edge correction (in the staged tile for the solve pass)
+                    const double bn = SOLVE ? sB[lp * WPITCH + lane] : bcol[(size_t)gp * p.nx] + corr[lp];
                     const double G = __builtin_fma(ka, D, c0.u - bn);
                     rhs = -G;
                     if (!SOLVE && owned) {
@@ -191,18 +199,18 @@ __device__ __forceinline__ void sweep(const double *sU, double *sB, const double
 // holds grid column bxo - HALO + lx (u) or bxo + lx. Every load covers (part of) one grid row, so its row
 // address is wave-uniform and only the column offset is per lane; all global loads are
 // issued before the first LDS store. Only the u cells the sweeps read are staged:
-// rows 0..67 x columns 1..66 (y sweep) and rows 1..66 x columns 0..67 (x sweep).
+// rows 0..67 (y sweep) or 1..66 (x sweep) of all 68 columns.
 template <int DIR, bool STAGE_B>
 __device__ __forceinline__ void stage_tile(const PassParams &p, double *sU, double *sB, int bxo, int y0, int wave,
                                            int lane)
 {
-    constexpr int LX0 = DIR == 0 ? 1 : 2;         // tile column of lane 0 in a row load
+    constexpr int LX0 = HALO;                     // tile column of lane 0 in a row load
     constexpr int RU0 = DIR == 0 ? 0 : 1;         // first u tile row read by the sweeps
     constexpr int NRU = DIR == 0 ? TW : TW - 2;   // u tile rows read by the sweeps
     constexpr int KU = (NRU + NSUB - 1) / NSUB;   // row loads per wave
     constexpr int KB = TILE / NSUB;
-    // the columns outside the lanes' span: 2 per row (y sweep) or 4 per row (x sweep)
-    constexpr int XPR = DIR == 0 ? 2 : 4;
+    // the columns outside the lanes' span: 2 on each side of every row
+    constexpr int XPR = 2 * HALO;
     constexpr int NX = NRU * XPR;
     constexpr int KX = (NX + BLOCK - 1) / BLOCK;  // packed extra loads per wave
     const int nx = p.nx, ny = p.ny;
@@ -231,7 +239,7 @@ __device__ __forceinline__ void stage_tile(const PassParams &p, double *sU, doub
         xoff[k] = -1;
         if (idx < NX) {
             const int ly = RU0 + idx / XPR, q = idx % XPR;
-            const int lx = DIR == 0 ? LX0 + 64 + q : (q < 2 ? q : 64 + q);
+            const int lx = q < HALO ? q : TILE + q;
             const int gy = crefl(y0 - HALO + ly, ny), gx = crefl(bxo - HALO + lx, nx);
             vx[k] = p.u[(size_t)gy * nx + gx];
             xoff[k] = ly * UPITCH + lx;
@@ -269,6 +277,8 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
     __shared__ double lds[NLDS];
     __shared__ double sRed[NSUB];
     __shared__ unsigned sFlag[NSUB];
+    // y relations pass: b^n corrections of lane 0, lane 63 and (zeros) the other lanes
+    __shared__ double sCorr[DIR == 0 && !SOLVE ? 3 * TILE : 1];
     double *const sU = lds;
     double *const sB = lds + NU;                 // second input, then exchange / output
     double *const xch = (SOLVE && !XU) ? sB : lds; // relation exchange
@@ -276,23 +286,22 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
     const int nx = p.nx, ny = p.ny;
     int x0, x1, y0, y1;
     if (DIR == 0) {
-        x0 = tx * LT0; x1 = min(x0 + LT0, nx);
+        x0 = tx * TILE; x1 = min(x0 + TILE, nx);
         y0 = seg_start(ty, ny); y1 = seg_start(ty + 1, ny);
     } else {
         x0 = seg_start(tx, nx); x1 = seg_start(tx + 1, nx);
         y0 = ty * TILE; y1 = min(y0 + TILE, ny);
     }
-    const int bxo = DIR == 0 ? x0 - 1 : x0;  // grid x of lane/position 0 of the tile
+    const int bxo = x0;  // grid x of lane/position 0 of the tile
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     stage_tile<DIR, STAGE_B>(p, sU, sB, bxo, y0, wave, lane);
     __syncthreads();
 
-    const int lane0 = DIR == 0 ? 1 : 0;                 // first lane that owns a line
     const int nlt = DIR == 0 ? x1 - x0 : y1 - y0;       // lines owned by the tile
-    const bool owned = lane >= lane0 && lane < lane0 + nlt;
-    const int gl = (DIR == 0 ? x0 - 1 : y0) + lane;     // grid line of this lane
+    const bool owned = lane < nlt;
+    const int gl = (DIR == 0 ? x0 : y0) + lane;         // grid line of this lane
     const int pbase = DIR == 0 ? y0 : x0;
     const int npos = DIR == 0 ? y1 - y0 : x1 - x0;      // segment length
     const int Nl = DIR == 0 ? nx : ny;
@@ -306,18 +315,43 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
     double rmax = 0.0;
     unsigned flags = 0;
 
+    // y sweep: the residual's x faces come from lane shuffles, so lanes 0 and 63 see zero flux
+    // through the tile's edge faces x0-1 | x0 and x0+63 | x0+64. That is made up for in b^n
+    // (G = u - b^n + ka D): at every position of the tile the edge face's flux F is formed
+    // here with the in-wave arithmetic, and ka F (lane 0) or -ka F (lane 63) is added to the
+    // lane's b^n, in the staged tile (solve) or as the sweep reads it (relations), the same
+    // sum in both passes. Faces on the domain edge carry no flux and take no correction; a
+    // flat film gets F = 0 and stays exact.
+    if (DIR == 0) {
+        if (tid < 2 * TILE) {
+            const bool right = tid >= TILE;
+            const int l = right ? TILE - 1 : -1, q = tid & (TILE - 1);
+            if (q < npos) {
+                const CellS L = cell_s<DIR, KM>(sU, p, l, q), R = cell_s<DIR, KM>(sU, p, l + 1, q);
+                const double F = __builtin_fma(L.f0 + R.f0, R.lap - L.lap, (L.f1 + R.f1) * (R.u - L.u));
+                const bool inner = right ? x1 < nx : x0 > 0;
+                const double c = !inner ? 0.0 : (right ? -(p.ka * F) : p.ka * F);
+                if (SOLVE && inner) sB[q * WPITCH + (right ? TILE - 1 : 0)] += c;
+                if (!SOLVE) sCorr[tid] = c;
+            }
+        } else if (!SOLVE && tid < 3 * TILE) {
+            sCorr[tid] = 0.0;
+        }
+        __syncthreads();
+    }
+
     // interior tiles take the specialised path (wave-uniform branch)
     const bool fast = npos == TILE && pbase >= 2 && pbase + TILE <= Np - 2
-                      && (DIR == 1 || (x0 > 0 && x0 + LT0 < nx && nlt == LT0));
+                      && (DIR == 1 || (x0 > 0 && x1 < nx));
     // per-lane column of b^n for the y relations pass (read from global memory)
     const double *bcol = DIR == 0 ? p.in2 + crefl(bxo + lane, nx)
                                   : p.in2 + (size_t)min(y0 + lane, ny - 1) * nx + (x0 + ps);
     if (len > 0) {
         if (fast)
-            sweep<DIR, SOLVE, KM, true>(sU, sB, bcol, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph,
+            sweep<DIR, SOLVE, KM, true>(sU, sB, sCorr, bcol, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph,
                                          fps, mine, rmax, flags);
         else
-            sweep<DIR, SOLVE, KM, false>(sU, sB, bcol, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph,
+            sweep<DIR, SOLVE, KM, false>(sU, sB, sCorr, bcol, p, lane, ps, len, pbase, Np, gl, Nl, owned, fa, fb, fz, fph,
                                           fps, mine, rmax, flags);
     }
 
@@ -826,7 +860,7 @@ __global__ void __launch_bounds__(256) k_flux_divergence(int nx, int ny, double 
     out[o] = (add != nullptr ? alpha * add[o] : 0.0) + beta * D;
 }
 
-// Ensemble b^n = u^n - (1 - theta) dt D(u^n), block -> one y-sweep tile (LT0 columns x one
+// Ensemble b^n = u^n - (1 - theta) dt D(u^n), block -> one y-sweep tile (TILE columns x one
 // segment of rows) of a film that is active and at the first iteration of its attempt (the
 // same arithmetic as k_flux_divergence with alpha = 1, so the ensemble matches the single film).
 __global__ void __launch_bounds__(256) k_bn_ens(EnsParams e)
@@ -841,7 +875,7 @@ __global__ void __launch_bounds__(256) k_bn_ens(EnsParams e)
     double *bn = e.bn + d.off;
     const double ids = 1.0 / d.ds, ids2 = ids * ids;
     const double beta = -(1.0 - e.theta) * s->dt;
-    const int i0 = tx * LT0, i1 = min(i0 + LT0, d.nx);
+    const int i0 = tx * TILE, i1 = min(i0 + TILE, d.nx);
     const int j0 = seg_start(ty, d.ny), j1 = seg_start(ty + 1, d.ny);
     const int w = i1 - i0;
     for (int c = threadIdx.x; c < w * (j1 - j0); c += 256) {

@@ -81,18 +81,17 @@ static void check_xcd_map()
     }
 }
 
-// y-sweep tiles own LT0 columns: every grid column exactly once; lanes 0 and 63 carry the
-// neighbouring columns
+// y-sweep tiles own TILE columns, one per lane: every grid column exactly once
 static void check_column_tiles()
 {
     for (int nx = 4; nx <= 5000; ++nx) {
-        const int tiles = (nx + LT0 - 1) / LT0;
+        const int tiles = (nx + TILE - 1) / TILE;
         int covered = 0;
         for (int tx = 0; tx < tiles; ++tx) {
-            const int x0 = tx * LT0, x1 = x0 + LT0 < nx ? x0 + LT0 : nx;
+            const int x0 = tx * TILE, x1 = x0 + TILE < nx ? x0 + TILE : nx;
             CHECK(x0 == covered && x1 > x0, "nx=%d tx=%d", nx, tx);
             covered = x1;
-            CHECK(x1 - x0 <= 64 - 2, "nx=%d tx=%d owned=%d", nx, tx, x1 - x0);
+            CHECK(x1 - x0 <= 64, "nx=%d tx=%d owned=%d", nx, tx, x1 - x0);
         }
         CHECK(covered == nx, "nx=%d", nx);
     }
@@ -104,8 +103,8 @@ static void check_tile_staging()
 {
     const int NU = TW * UPITCH, NW = TILE * WPITCH;
     for (int dir = 0; dir < 2; ++dir) {
-        const int LX0 = dir == 0 ? 1 : 2, RU0 = dir == 0 ? 0 : 1, NRU = dir == 0 ? TW : TW - 2;
-        const int KU = (NRU + NSUB - 1) / NSUB, KB = TILE / NSUB, XPR = dir == 0 ? 2 : 4;
+        const int LX0 = HALO, RU0 = dir == 0 ? 0 : 1, NRU = dir == 0 ? TW : TW - 2;
+        const int KU = (NRU + NSUB - 1) / NSUB, KB = TILE / NSUB, XPR = 2 * HALO;
         const int NX = NRU * XPR, KX = (NX + BLOCK - 1) / BLOCK;
         std::vector<int> hit(NU, 0);
         for (int wave = 0; wave < NSUB; ++wave)
@@ -126,19 +125,30 @@ static void check_tile_staging()
                     const int idx = (wave + NSUB * k) * 64 + lane;
                     if (idx < NX) {
                         const int ly = RU0 + idx / XPR, q = idx % XPR;
-                        const int lx = dir == 0 ? LX0 + 64 + q : (q < 2 ? q : 64 + q);
+                        const int lx = q < HALO ? q : TILE + q;
                         const int i = ly * UPITCH + lx;
                         CHECK(lx < TW && i >= 0 && i < NU, "dir=%d extra index %d", dir, i);
                         if (i >= 0 && i < NU) hit[i]++;
                     }
                 }
             }
-        // the cells the sweeps read: y sweep rows 0..TW-1 x columns 1..TW-2; x sweep rows
-        // 1..TW-2 x columns 0..TW-1; each staged exactly once
-        for (int ly = RU0; ly < RU0 + NRU; ++ly)
-            for (int lx = (dir == 0 ? 1 : 0); lx < (dir == 0 ? TW - 1 : TW); ++lx)
-                CHECK(hit[ly * UPITCH + lx] == 1, "dir=%d cell (%d,%d) staged %d times", dir, ly, lx,
-                      hit[ly * UPITCH + lx]);
+        // the cells the sweeps read, each staged exactly once: the cell quantities of (line l,
+        // position q) read u at (l, q), (l +- 1, q) and (l, q +- 1); the sweeps form them for
+        // every lane at positions -1..TILE, the y sweep's edge record for the lines -1, 0,
+        // TILE-1 and TILE at positions 0..TILE-1
+        std::vector<int> need(NU, 0);
+        auto at = [&](int l, int q) {
+            const int i = dir == 0 ? (q + HALO) * UPITCH + (l + HALO) : (l + HALO) * UPITCH + (q + HALO);
+            CHECK(i >= 0 && i < NU, "dir=%d read (%d,%d) outside the tile", dir, l, q);
+            if (i >= 0 && i < NU) need[i] = 1;
+        };
+        auto cell = [&](int l, int q) { at(l, q); at(l - 1, q); at(l + 1, q); at(l, q - 1); at(l, q + 1); };
+        for (int l = 0; l < TILE; ++l)
+            for (int q = -1; q <= TILE; ++q) cell(l, q);
+        if (dir == 0)
+            for (int q = 0; q < TILE; ++q) { cell(-1, q); cell(0, q); cell(TILE - 1, q); cell(TILE, q); }
+        for (int i = 0; i < NU; ++i)
+            if (need[i]) CHECK(hit[i] == 1, "dir=%d cell (%d,%d) staged %d times", dir, i / UPITCH, i % UPITCH, hit[i]);
     }
 }
 
