@@ -218,14 +218,7 @@ __global__ void __launch_bounds__(BLOCK) k_sb_pass(SBParams P)
             Rel first;
             load_rel(sB, 0, lane, first);
             chain_symbolic(first, sB + NREL * 64, lane, nsub, seg);
-            double *o = P.rel + (size_t)q * NREL * P.nl + line;
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 5; ++j) {
-                    o[(size_t)(i * 5 + j) * P.nl] = seg.T[i][j];
-                    o[(size_t)(10 + i * 5 + j) * P.nl] = seg.B[i][j];
-                }
+            rel_store(P.rel + (size_t)q * NREL * P.nl + 2 * (size_t)line, P.nl, seg);
         }
         return;
     }

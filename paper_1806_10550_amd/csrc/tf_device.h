@@ -182,6 +182,42 @@ struct Rel {
     double T[2][5], B[2][5];
 };
 
+// Relation records (NREL doubles per (segment, line)) and chain records (NCHAIN) in global
+// memory hold the fields of a record in pairs: in a block of records of NL lines, field f of
+// line l sits at 2 (f / 2) NL + 2 l + f % 2, so that a lane moves two fields with one 16-byte
+// access and the accesses of a wave are contiguous. `r` points at the block advanced by 2 l.
+// (Boundary records, NEXT doubles, keep one field per array: field f of line l at f NL + l.)
+__device__ __forceinline__ double2 rec_get2(const double *r, size_t NL, int k)
+{
+    return *reinterpret_cast<const double2 *>(r + 2 * (size_t)k * NL);
+}
+__device__ __forceinline__ void rec_put2(double *r, size_t NL, int k, double a, double b)
+{
+    *reinterpret_cast<double2 *>(r + 2 * (size_t)k * NL) = make_double2(a, b);
+}
+
+// Field f (record order T[0][0..4], T[1][0..4], B[0][0..4], B[1][0..4]) of a relation record.
+__device__ __forceinline__ double &rel_field(Rel &S, int f)
+{
+    return f < 10 ? S.T[f / 5][f % 5] : S.B[(f - 10) / 5][(f - 10) % 5];
+}
+
+// A relation record to / from global memory (paired layout above).
+__device__ __forceinline__ void rel_store(double *r, size_t NL, Rel S)
+{
+#pragma unroll
+    for (int k = 0; k < NREL / 2; ++k) rec_put2(r, NL, k, rel_field(S, 2 * k), rel_field(S, 2 * k + 1));
+}
+__device__ __forceinline__ void rel_fetch(const double *r, size_t NL, Rel &S)
+{
+#pragma unroll
+    for (int k = 0; k < NREL / 2; ++k) {
+        const double2 v = rec_get2(r, NL, k);
+        rel_field(S, 2 * k) = v.x;
+        rel_field(S, 2 * k + 1) = v.y;
+    }
+}
+
 // Relation record q of this lane from the LDS exchange area.
 __device__ __forceinline__ void load_rel(const double *sB, int q, int lane, Rel &S)
 {

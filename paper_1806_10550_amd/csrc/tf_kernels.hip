@@ -396,14 +396,7 @@ __device__ __forceinline__ void tile_body(const PassParams &p, int tx, int ty)
         if (wave == 0 && owned) {
             Rel seg;
             chain_symbolic(mine, xch, lane, nsub, seg);
-            double *o = p.rel + (size_t)qseg * NREL * Nl;
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 5; ++j) {
-                    (o + (size_t)(i * 5 + j) * Nl)[(unsigned)gl] = seg.T[i][j];
-                    (o + (size_t)(10 + i * 5 + j) * Nl)[(unsigned)gl] = seg.B[i][j];
-                }
+            rel_store(p.rel + (size_t)qseg * NREL * Nl + 2 * (size_t)(unsigned)gl, Nl, seg);
         }
         return;
     }
@@ -572,18 +565,23 @@ __global__ void TF_PASS_ATTR k_pass_ens(EnsParams e)
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ void load_rec(const double *r, size_t NL, double (&T)[2][5], double (&B)[2][5])
 {
+    Rel S;
+    rel_fetch(r, NL, S);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-            T[i][j] = r[(size_t)(i * 5 + j) * NL];
-            B[i][j] = r[(size_t)(10 + i * 5 + j) * NL];
+            T[i][j] = S.T[i][j];
+            B[i][j] = S.B[i][j];
         }
 }
 
+// Six fields (a0, a1, X) of a chain record from field 0 of `w` (paired layout).
 __device__ __forceinline__ void store6(double *w, size_t NL, double a0, double a1, const M2 &X)
 {
-    w[0] = a0; w[NL] = a1; w[2 * NL] = X.a; w[3 * NL] = X.b; w[4 * NL] = X.c; w[5 * NL] = X.d;
+    rec_put2(w, NL, 0, a0, a1);
+    rec_put2(w, NL, 1, X.a, X.b);
+    rec_put2(w, NL, 2, X.c, X.d);
 }
 
 // Meeting record of one line: the forward wave leaves (bt_{m-1}, M_{m-1}), the backward
@@ -605,8 +603,8 @@ __device__ __forceinline__ void chain_line(const ChainParams &c, int line, int w
     const size_t RS = (size_t)NREL * NL, CS = (size_t)NCHAIN * NL, ES = (size_t)NEXT * NL;
     const int P = c.P, m = P / 2;
     const bool live = line < c.nlines;
-    const double *rb = c.rel + line;
-    double *cb = c.chain + line;
+    const double *rb = c.rel + 2 * (size_t)line;
+    double *cb = c.chain + 2 * (size_t)line;
     double *eb = c.ext + line;
     double x0 = 0.0, x1 = 0.0;   // wave 0: bt_q; wave 1: tt_q
     M2 X = {0, 0, 0, 0};         // wave 0: M_q;  wave 1: R_q
@@ -717,7 +715,11 @@ __device__ __forceinline__ void chain_line(const ChainParams &c, int line, int w
     double RA[D][6], RN[D][6];
     auto ld6 = [&](const double *w, double (&o)[6]) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) o[k] = w[(size_t)k * NL];
+        for (int k = 0; k < 3; ++k) {
+            const double2 v = rec_get2(w, NL, k);
+            o[2 * k] = v.x;
+            o[2 * k + 1] = v.y;
+        }
     };
     if (wave == 0) {
         // q = m-1..0: T_q = tau_q + N_q T_{q+1}, B_{q-1} = bt_{q-1} + M_{q-1} T_q
