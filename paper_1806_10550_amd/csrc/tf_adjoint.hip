@@ -494,14 +494,34 @@ __device__ __forceinline__ void jdt_cell(int nx, int ny, double ids, double ids2
 // forms xi on the tile and its one-cell ring (ghost positions take the reflected cell's
 // value) and local on the tile in LDS, then applies the Laplacian to xi from LDS.
 // clr (nullable): two reduction words zeroed for a later kernel of the stream.
+// Richardson iterations enqueued in a batch (ctl non-null): ctl[0] is the stop word. A
+// launch that finds it set does nothing; one that finds the previous iteration's record
+// chk = {max|z|, max|mu|} converged (max|z| <= tol max|mu|) or NaN does nothing either and
+// sets ctl[0] (1: converged, 2: NaN) and ctl[1] = it - 1, the converged iteration. Every
+// workgroup reads the same record, so all take the same decision.
 constexpr int JT_X = 64, JT_Y = 16;
 template <bool P32>
 __global__ void __launch_bounds__(256) k_jdt(int nx, int ny, double ids, double ids2, Model M, const double *u,
                                              const double *mu, const double *lam, double a, double b, double g,
-                                             double *out, unsigned long long *clr)
+                                             double *out, unsigned long long *clr, const unsigned long long *chk,
+                                             unsigned long long *ctl, double tol, int it)
 {
     constexpr int RX = JT_X + 2, RY = JT_Y + 2;
     __shared__ double sxi[RY * RX], sloc[RY * RX];
+    if (ctl != nullptr) {
+        if (ctl[0] != 0ull) return;
+        if (chk != nullptr) {
+            const double zmax = __longlong_as_double((long long)chk[0]), mmax = __longlong_as_double((long long)chk[1]);
+            const bool nan = !(zmax == zmax) || !(mmax == mmax);
+            if (nan || zmax <= tol * mmax) {
+                if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+                    ctl[1] = (unsigned long long)(it - 1);
+                    ctl[0] = nan ? 2ull : 1ull;
+                }
+                return;
+            }
+        }
+    }
     if (clr != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) clr[threadIdx.x] = 0ull;
     const int i0 = blockIdx.x * JT_X, j0 = blockIdx.y * JT_Y;
     for (int e = threadIdx.x; e < RX * RY; e += 256) {
@@ -712,14 +732,16 @@ namespace {
 // rowio: rhs and out line-major (transposed MODE 0 solves of the partitioned variant, and
 // of the whole-line variant, whose bands are then line-major too).
 tf_status sb_solve(Choice ch, bool trans, int mode, int nl, int np, const double *bands, const double *rhs,
-                   double *out, unsigned long long *red, const Scratch &S, hipStream_t s, bool rowio = false)
+                   double *out, unsigned long long *red, const Scratch &S, hipStream_t s, bool rowio = false,
+                   const unsigned long long *stop = nullptr)
 {
+    // (stop: honoured by the whole-line solver only; the callers pass it for that variant)
     tf::SBParams P{nl, np, bands, rhs, out, S.rel, S.ext, red};
     if (rowio && ((ch.variant != V_PARTITIONED && ch.variant != V_LINE) || !trans || mode != 0))
         return afail(TF_EINVAL, "line-major solves need a transposed MODE 0 partitioned or whole-line solve");
     if (ch.variant == V_LINE) {
         if (!tf::sbline_supported(np)) return afail(TF_EINVAL, "the whole-line solver needs 4 <= n <= 4096");
-        TF_AHIP(tf::launch_sbline(trans, !rowio, mode, nl, np, bands, rhs, out, red, s));
+        TF_AHIP(tf::launch_sbline(trans, !rowio, mode, nl, np, bands, rhs, out, red, s, stop));
         return TF_OK;
     }
     if (ch.variant == V_PCR) {
@@ -765,6 +787,7 @@ struct AdjBuffers {
     double *dk1 = nullptr, *dk0 = nullptr, *work = nullptr, *part = nullptr;
     double *hpart = nullptr;
     unsigned long long *red = nullptr, *hred = nullptr;
+    int last_iters = 0; // Richardson iterations of the previous adjoint step (batch size)
 };
 
 std::mutex g_adj_mu;
@@ -812,12 +835,17 @@ tf_status get_adj(const tf_grid *g, int nx, int ny, AdjBuffers **out)
 }
 
 tf_status jdt(const tf_detail::GridView &v, const double *u, const double *mu, const double *lam, double a, double b,
-              double gmul, double *out, unsigned long long *clr = nullptr)
+              double gmul, double *out, unsigned long long *clr = nullptr, const unsigned long long *chk = nullptr,
+              unsigned long long *ctl = nullptr, double tol = 0.0, int it = 0)
 {
     const double ids = 1.0 / v.ds, ids2 = ids * ids;
     const dim3 grid((v.nx + tf::JT_X - 1) / tf::JT_X, (v.ny + tf::JT_Y - 1) / tf::JT_Y), blk(256);
-    if (v.M.p32) tf::k_jdt<true><<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids, ids2, v.M, u, mu, lam, a, b, gmul, out, clr);
-    else tf::k_jdt<false><<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids, ids2, v.M, u, mu, lam, a, b, gmul, out, clr);
+    if (v.M.p32)
+        tf::k_jdt<true><<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids, ids2, v.M, u, mu, lam, a, b, gmul, out, clr, chk,
+                                                     ctl, tol, it);
+    else
+        tf::k_jdt<false><<<grid, blk, 0, v.stream>>>(v.nx, v.ny, ids, ids2, v.M, u, mu, lam, a, b, gmul, out, clr, chk,
+                                                      ctl, tol, it);
     TF_AHIP(hipGetLastError());
     return TF_OK;
 }
@@ -972,35 +1000,58 @@ tf_status tf_adjoint_step(tf_grid *g, const double *h_n, const double *h_np1, do
     // initial guess mu = lambda^{n+1} (the solution for dt -> 0; only the number of
     // iterations depends on it)
     TF_AHIP(hipMemcpyAsync(B.mu, lambda_inout, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-    int it;
+    // Iteration i keeps its reduction record {max|z|, max|mu|} in red[2 (i % 2) ..]. When both
+    // solves are whole-line kernels, whose launches can stand down on the device, the
+    // iterations are enqueued in batches (one more than the previous step needed) and each
+    // launch of J_D^T first tests the previous iteration's record (red[4..5]: stop word and
+    // converged iteration): the host then waits once per batch instead of once per
+    // iteration, and the iterates are those of a test after every iteration.
+    const bool batched = rowx && vy.variant == V_LINE;
+    unsigned long long *ctl = batched ? B.red + 4 : nullptr;
+    if (batched) TF_AHIP(hipMemsetAsync(B.red + 4, 0, 2 * sizeof(unsigned long long), s));
+    int it = 0;
     bool conv = false;
-    for (it = 1; it <= max_iter; ++it) {
-        // r = lambda - (I + c J^T) mu
-        // (the reduction words of this iteration's y solve are zeroed by the same kernel)
-        if ((st = jdt(v, h_np1, B.mu, lambda_inout, 1.0, -1.0, -c, B.r, B.red)) != TF_OK) return st;
-        // (I + c J_x)^-T: rows as lines; the whole-row kernel and the partitioned solver
-        // read r and write y row by row, the other variants work on the transposed layout
-        if (rowx) {
-            if ((st = sb_solve(Choice{V_LINE, 256}, true, 0, ny, nx, B.bx, B.r, B.y, nullptr, S, s, true)) != TF_OK)
+    while (it < max_iter && !conv) {
+        const int nb = batched ? std::min(std::max(B.last_iters + 1, 2), max_iter - it) : 1;
+        for (int k = 1; k <= nb; ++k) {
+            const int i = it + k;
+            unsigned long long *cur = B.red + 2 * (i & 1), *prev = B.red + 2 * ((i - 1) & 1);
+            // r = lambda - (I + c J^T) mu (this kernel also zeroes the iteration's record)
+            if ((st = jdt(v, h_np1, B.mu, lambda_inout, 1.0, -1.0, -c, B.r, cur, k > 1 ? prev : nullptr, ctl, tol,
+                          i)) != TF_OK)
                 return st;
-        } else if (vx.variant == V_PARTITIONED) {
-            if ((st = sb_solve(vx, true, 0, ny, nx, B.bx, B.r, B.y, nullptr, S, s, true)) != TF_OK) return st;
-        } else {
-            if ((st = transpose(ny, nx, B.r, B.rT, s)) != TF_OK) return st;
-            if ((st = sb_solve(vx, true, 0, ny, nx, B.bx, B.rT, B.yT, nullptr, S, s)) != TF_OK) return st;
-            if ((st = transpose(nx, ny, B.yT, B.y, s)) != TF_OK) return st;
+            // (I + c J_x)^-T: rows as lines; the whole-row kernel and the partitioned solver
+            // read r and write y row by row, the other variants work on the transposed layout
+            if (rowx) {
+                if ((st = sb_solve(Choice{V_LINE, 256}, true, 0, ny, nx, B.bx, B.r, B.y, nullptr, S, s, true, ctl)) !=
+                    TF_OK)
+                    return st;
+            } else if (vx.variant == V_PARTITIONED) {
+                if ((st = sb_solve(vx, true, 0, ny, nx, B.bx, B.r, B.y, nullptr, S, s, true)) != TF_OK) return st;
+            } else {
+                if ((st = transpose(ny, nx, B.r, B.rT, s)) != TF_OK) return st;
+                if ((st = sb_solve(vx, true, 0, ny, nx, B.bx, B.rT, B.yT, nullptr, S, s)) != TF_OK) return st;
+                if ((st = transpose(nx, ny, B.yT, B.y, s)) != TF_OK) return st;
+            }
+            // (I + c J_y)^-T: columns as lines; mu += z with max|z|, max|mu|
+            if ((st = sb_solve(vy, true, 1, nx, ny, B.by, B.y, B.mu, cur, S, s, false, ctl)) != TF_OK) return st;
         }
-        // (I + c J_y)^-T: columns as lines; mu += z with max|z|, max|mu|
-        if ((st = sb_solve(vy, true, 1, nx, ny, B.by, B.y, B.mu, B.red, S, s)) != TF_OK) return st;
-        TF_AHIP(hipMemcpyAsync(B.hred, B.red, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        const int last = it + nb;
+        TF_AHIP(hipMemcpyAsync(B.hred, B.red, 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         TF_AHIP(hipStreamSynchronize(s));
-        const double zmax = bits_to_double(B.hred[0]), mmax = bits_to_double(B.hred[1]);
-        if (!(zmax == zmax) || !(mmax == mmax)) return afail(TF_ENONPOS, "adjoint iteration produced NaN");
-        if (zmax <= tol * mmax) {
+        if (batched && B.hred[4] != 0ull) {
+            if (B.hred[4] == 2ull) return afail(TF_ENONPOS, "adjoint iteration produced NaN");
+            it = (int)B.hred[5];
             conv = true;
             break;
         }
+        const unsigned long long *rec = B.hred + 2 * (last & 1);
+        const double zmax = bits_to_double(rec[0]), mmax = bits_to_double(rec[1]);
+        if (!(zmax == zmax) || !(mmax == mmax)) return afail(TF_ENONPOS, "adjoint iteration produced NaN");
+        it = last;
+        conv = zmax <= tol * mmax;
     }
+    if (conv) B.last_iters = it;
     if (iters_out) *iters_out = conv ? it : max_iter;
     if (!conv) return afail(TF_ENOCONV, "adjoint Richardson iteration did not converge");
     size_t dot_blocks = 0;

@@ -210,10 +210,12 @@ int xrow_blocks(int nx, int ny);           // workgroups of one launch (= mass r
 hipError_t launch_xrow(const PassParams &p, hipStream_t s);
 // Stored-band solves of whole lines (4 ..= XR_ROW4_MAX_NX cells) in one kernel: pm true
 // position-major (plain or transposed; mode 0 out = x, mode 1 out += x with the maxima in
-// red[0..1]), pm false line-major (transposed, mode 0 only).
+// red[0..1]), pm false line-major (transposed, mode 0 only). stop (nullable): a device word;
+// when it is nonzero as the kernel starts, the kernel does nothing.
 bool sbline_supported(int np);
 hipError_t launch_sbline(bool trans, bool pm, int mode, int nl, int np, const double *bands, const double *rhs,
-                         double *out, unsigned long long *red, hipStream_t s);
+                         double *out, unsigned long long *red, hipStream_t s,
+                         const unsigned long long *stop = nullptr);
 // x-sweep variant for a film of nx x ny cells (0: partitioned, 1: whole-row): the autotuned
 // choice for the nearest shape, else the built-in rule (tf_adjoint.hip).
 int xsweep_choice(int nx, int ny);

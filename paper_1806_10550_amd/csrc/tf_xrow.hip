@@ -534,8 +534,9 @@ hipError_t launch_xrow_ens(int km, const EnsParams &e, hipStream_t s)
 template <bool TRANS, bool PM, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_sbline(int nl, int np, const double *bands, const double *rhs, double *out, unsigned long long *red, XRowGeom g,
-         int nblocks)
+         int nblocks, const unsigned long long *stop)
 {
+    if (stop != nullptr && *stop != 0ull) return; // a converged iteration (the whole workgroup leaves)
     __shared__ double lds[xr_lds(4)];
     __shared__ double sRed[4][2];
     constexpr int CPL = XR_CPL;
@@ -624,18 +625,18 @@ k_sbline(int nl, int np, const double *bands, const double *rhs, double *out, un
 bool sbline_supported(int np) { return np <= XR_ROW4_MAX_NX && xrow_supported(np); }
 
 hipError_t launch_sbline(bool trans, bool pm, int mode, int nl, int np, const double *bands, const double *rhs,
-                         double *out, unsigned long long *red, hipStream_t s)
+                         double *out, unsigned long long *red, hipStream_t s, const unsigned long long *stop)
 {
     if (nl < 1 || !sbline_supported(np) || (mode == 1 && red == nullptr) || (!pm && (!trans || mode != 0)))
         return hipErrorInvalidValue;
     const XRowGeom g = xrow_geom(np); // 4-wave workgroups for lines of at most XR_ROW4_MAX_NX cells
     const int nb = (nl + g.R - 1) / g.R;
     const dim3 grid(nb), block(64 * g.W * g.R);
-    if (!pm) k_sbline<true, false, 0><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb);
-    else if (trans && mode == 0) k_sbline<true, true, 0><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb);
-    else if (trans) k_sbline<true, true, 1><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb);
-    else if (mode == 0) k_sbline<false, true, 0><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb);
-    else k_sbline<false, true, 1><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb);
+    if (!pm) k_sbline<true, false, 0><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb, stop);
+    else if (trans && mode == 0) k_sbline<true, true, 0><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb, stop);
+    else if (trans) k_sbline<true, true, 1><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb, stop);
+    else if (mode == 0) k_sbline<false, true, 0><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb, stop);
+    else k_sbline<false, true, 1><<<grid, block, 0, s>>>(nl, np, bands, rhs, out, red, g, nb, stop);
     return hipGetLastError();
 }
 
