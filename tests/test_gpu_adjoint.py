@@ -311,6 +311,53 @@ def test_512_adjoint_step_matches_oracle(adjoint512_step, xsweep):
     assert gk == pytest.approx(gk_ref, rel=1e-9)
 
 
+def test_512_adjoint_batched_richardson_iterations(adjoint512_step):
+    """At 512^2 both transposed solves are whole-line kernels, so the Richardson iterations
+    run in batches whose launches test the previous iteration on the device. The result and
+    the iteration count do not depend on the batch size the grid's previous step left; a limit
+    of exactly the iterations needed converges to the same result, one fewer fails with
+    TF_ENOCONV, and a NaN in lambda is reported as TF_ENONPOS."""
+    import os
+    import paper_1806_10550_amd as pkg
+    from paper_1806_10550_amd.lib import TF_ENOCONV, TF_ENONPOS
+    autotune_load(os.path.join(os.path.dirname(pkg.__file__), "autotune_gfx950.jsonl"))
+    assert autotune_choice(512, 512, transposed=True) == "line"
+    un, unp1, lam, ref, gk_ref = adjoint512_step
+    cfg = synth.CONFIGS["adjoint512"]
+    n, ds, dt = cfg.n, cfg.ds, cfg.dt
+    g = grid(n, n, ds)
+    g.set_xsweep("row")
+    hn, hnp1 = gpu(un), gpu(unp1)
+
+    def run(lam_in, **kw):
+        lg = gpu(lam_in)
+        gk, it = g.adjoint_step(hn, hnp1, dt, lg, **kw)
+        return lg, gk, it
+
+    l1, gk1, it1 = run(lam, tol=1e-13)      # first step of the grid: the smallest batch
+    assert np.max(np.abs(l1.cpu().numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
+    assert gk1 == pytest.approx(gk_ref, rel=1e-9)
+    assert it1 > 2
+    l2, gk2, it2 = run(lam, tol=1e-13)      # batch sized from it1
+    assert it2 == it1 and torch.equal(l2, l1) and gk2 == gk1
+    _, _, it3 = run(lam, tol=1e-4)          # fewer iterations: a smaller next batch
+    assert it3 < it1
+    l4, gk4, it4 = run(lam, tol=1e-13)
+    assert it4 == it1 and torch.equal(l4, l1) and gk4 == gk1
+    l5, gk5, it5 = run(lam, tol=1e-13, max_iter=it1)
+    assert it5 == it1 and torch.equal(l5, l1) and gk5 == gk1
+    with pytest.raises(TFError) as e:
+        run(lam, tol=1e-13, max_iter=it1 - 1)
+    assert e.value.status == TF_ENOCONV
+    bad = lam.copy()
+    bad[7, 9] = np.nan
+    with pytest.raises(TFError) as e:
+        run(bad, tol=1e-13)
+    assert e.value.status == TF_ENONPOS
+    l6, gk6, it6 = run(lam, tol=1e-13)      # the grid recovers
+    assert it6 == it1 and torch.equal(l6, l1) and gk6 == gk1
+
+
 def test_full_size_rollout_gradient_matches_finite_differences():
     """The 512^2 adjoint workload as timed (L = 16 lambda_m, 400 backward-Euler steps of dt = 0.1,
     checkpoints every 20, p0 = 0 on the seed-4 film, target = the seed-5 film run forward over the
