@@ -36,7 +36,10 @@ def make_grid(nx, ny, ds, theta=1.0, **kw):
 
 
 SHAPES = [(4, 4), (5, 7), (37, 23), (64, 64), (65, 64), (64, 65), (128, 128), (129, 70), (130, 67), (70, 193), (200, 9),
-          (4, 257), (257, 5), (62, 62), (63, 20), (125, 66)]
+          (4, 257), (257, 5), (62, 62), (63, 20), (125, 66),
+          # tiles inside the film on all four sides (the interior fast path; the y-sweep
+          # edge-face corrections on both sides of a tile)
+          (200, 200), (193, 196), (192, 130)]
 
 
 @pytest.mark.parametrize("nx,ny", SHAPES)
