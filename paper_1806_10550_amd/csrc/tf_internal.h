@@ -37,9 +37,16 @@ __host__ __device__ constexpr int xr_lds(int waves) { return waves * 2400; }
 constexpr int XR_ROW4_MAX_NX = XR_CPL * 64 * 4;      // rows a 4-wave workgroup holds
 
 // Geometry of the whole-row sweep and of the whole-line solver (host and device).
-// LDS index of position i (>= 0) of a staged row: one padding double every 16, so that
-// lanes reading 16 consecutive cells each (stride 17 doubles) hit distinct banks.
-__host__ __device__ inline int xr_pad(int i) { return i + (i >> 4); }
+// A row of nx cells is held by S = ceil(nx / 16) lanes; lane s owns the 16 positions
+// q = nx - 16 (S - s) + k, k < 16 (lane 0 may start before the row). Staged rows number
+// their positions w = q + 16 S - nx = 16 s + k from lane 0's first one (w >= -2 covers the two
+// cells before it) and store them at xr_at(w): one padding double every 16, so that lanes
+// reading their cells in step (stride 17 doubles) hit distinct banks, and lane s's block
+// starts at 17 s + 3, so that a lane's accesses sit at constant offsets xr_off(t) of its
+// block (t = k + d, -2 <= t).
+__host__ __device__ inline int xr_at(int w) { return w + 3 + (w >> 4); }
+__host__ __device__ constexpr int xr_off(int t) { return t + (t >> 4); }
+__host__ __device__ inline int xr_base(int s) { return 17 * s + 3; }
 
 // Geometry of one launch (host computed, identical for every row of the grid).
 struct XRowGeom {
@@ -50,9 +57,7 @@ struct XRowGeom {
     int waves;    // waves per workgroup (4 or 8)
 };
 
-__host__ __device__ inline int xr_cells_u(int nx) { return xr_pad(nx + 4) + 1; }
-
-// Staging loads per thread: nx + 4 <= 64 W XR_CPL + 4 cells over 64 W threads.
+// Staging loads per thread: 16 S + 4 <= 64 W XR_CPL + 4 cells over 64 W threads.
 constexpr int XR_STAGE = XR_CPL + 1;
 
 __host__ __device__ inline XRowGeom xrow_geom(int nx)
@@ -60,10 +65,9 @@ __host__ __device__ inline XRowGeom xrow_geom(int nx)
     XRowGeom g{};
     g.S = (nx + XR_CPL - 1) / XR_CPL;
     g.W = (g.S + 63) / 64;
-    g.pu = xr_cells_u(nx);
-    const int px = xr_pad(nx + 2) + 1, pt = NREL * g.S, pv = xr_pad(nx) + 1;
+    g.pu = xr_at(XR_CPL * g.S + 1) + 1;                // u row: w = -2 .. 16 S + 1
+    const int px = xr_at(XR_CPL * g.S) + 1, pt = NREL * g.S; // u(j-1) + u(j+1): w = -1 .. 16 S
     g.p2 = px > pt ? px : pt;
-    if (pv > g.p2) g.p2 = pv;
     g.waves = g.W <= 4 ? 4 : XR_WAVES;
     g.R = g.waves / g.W;
     if (g.R < 1) g.R = 1;

@@ -253,24 +253,22 @@ __device__ __forceinline__ void xr_tree(double *rec, int S, int tr, bool row_ok)
 // Back-substitution of slot s from its outer pairs (fields 0..3 of the slot after the tree);
 // the coefficient ps of l2 waits in the LDS slot of each position (parked there before the
 // tree) and the solution replaces it.
-// (lnear: the lane may hold padding positions gp < 0, which have no slot)
 template <int CPL>
-__device__ __forceinline__ void xr_backsub(const double *rec, int S, int s, int p0, bool lnear, double *slots,
+__device__ __forceinline__ void xr_backsub(const double *rec, int S, int s, double *slots,
                                            const double (&fa)[CPL], const double (&fb)[CPL], const double (&fz)[CPL],
                                            const double (&fph)[CPL])
 {
+    // slots: this lane's block (position k at slots[k]); positions before the row are
+    // identity rows and solve to zero
     const double l1 = rec[0 * S + s], l2 = rec[1 * S + s];
     double x1 = rec[2 * S + s], x2 = rec[3 * S + s];
 #pragma unroll
     for (int k = CPL - 1; k >= 0; --k) {
-        const int gp = p0 + k;
-        if (!lnear || gp >= 0) {
-            double *slot = slots + xr_pad(gp);
-            const double v = fz[k] + fph[k] * l1 + *slot * l2 - fa[k] * x1 - fb[k] * x2;
-            *slot = v;
-            x2 = x1;
-            x1 = v;
-        }
+        double *slot = slots + k;
+        const double v = fz[k] + fph[k] * l1 + *slot * l2 - fa[k] * x1 - fb[k] * x2;
+        *slot = v;
+        x2 = x1;
+        x1 = v;
     }
 }
 
@@ -298,9 +296,11 @@ __device__ __forceinline__ void xrow_body(const PassParams &p, const XRowGeom &g
     double *const sX = sU + g.pu;                    // u_N + u_S, then the tree
     const double ka = p.ka;
     const int S = g.S;
+    const int sh = CPL * S - nx;                     // staged index w = q + sh
 
-    // ---- stage u(j) with two ghost cells each side and u(j-1) + u(j+1) with one; every
-    // global load of a thread is issued before its first LDS store
+    // ---- stage u(j) at w = -2 .. 16 S + 1 (two ghost cells each side) and u(j-1) + u(j+1)
+    // at w = -1 .. 16 S (one); positions before lane 0's ghosts hold the first ghost's value.
+    // Every global load of a thread is issued before its first LDS store.
     if (row_ok) {
         const double *uc = p.u + (size_t)j * nx;
         const double *un = p.u + (size_t)crefl(j - 1, ny) * nx;
@@ -308,18 +308,18 @@ __device__ __forceinline__ void xrow_body(const PassParams &p, const XRowGeom &g
         double vu[XR_STAGE], vx[XR_STAGE];
 #pragma unroll
         for (int k = 0; k < XR_STAGE; ++k) {
-            const int i = tr + k * nthr;
-            if (i < nx + 4) vu[k] = uc[crefl(i - 2, nx)];
-            if (i < nx + 2) {
-                const int c = crefl(i - 1, nx);
+            const int i = tr + k * nthr;            // w = i - 2 (u row), i - 1 (X row)
+            if (i < CPL * S + 4) vu[k] = uc[crefl(max(i - 2 - sh, -2), nx)];
+            if (i < CPL * S + 2) {
+                const int c = crefl(max(i - 1 - sh, -1), nx);
                 vx[k] = us[c] + un[c];
             }
         }
 #pragma unroll
         for (int k = 0; k < XR_STAGE; ++k) {
             const int i = tr + k * nthr;
-            if (i < nx + 4) sU[xr_pad(i)] = vu[k];
-            if (i < nx + 2) sX[xr_pad(i)] = vx[k];
+            if (i < CPL * S + 4) sU[xr_at(i - 2)] = vu[k];
+            if (i < CPL * S + 2) sX[xr_at(i - 1)] = vx[k];
         }
     }
     const bool act = row_ok && s < S;
@@ -335,24 +335,24 @@ __device__ __forceinline__ void xrow_body(const PassParams &p, const XRowGeom &g
     }
     __syncthreads();
 
-    // u and ds^2 times the 5-point Laplacian at position q >= -1
-    auto U = [&](int q) { return sU[xr_pad(q + 2)]; };
-    auto cell = [&](int q) {
-        q = max(q, -1);
-        const double uq = U(q);
-        return cell_core<KM>(p, uq, __builtin_fma(-4.0, uq, (U(q + 1) + U(q - 1)) + sX[xr_pad(q + 1)]));
+    // u and ds^2 times the 5-point Laplacian at position p0 + t of this lane (t >= -1)
+    const int base = xr_base(s);
+    auto U = [&](int t) { return sU[base + xr_off(t)]; };
+    auto cell = [&](int t) {
+        const double uq = U(t);
+        return cell_core<KM>(p, uq, __builtin_fma(-4.0, uq, (U(t + 1) + U(t - 1)) + sX[base + xr_off(t)]));
     };
     // phase 1: assemble and eliminate the sub-segment with its outer unknowns l1 = x_{p0-2},
     // l2 = x_{p0-1} kept symbolic (z: constant part, ph: coefficient of l1, ps: of l2); the
     // factors stay in registers for the back-substitution
     double fa[CPL], fb[CPL], fz[CPL], fph[CPL], fps[CPL];
     if (act) {
-        CellS c0 = cell(p0);
-        FaceS fm = face_s<false>(cell(p0 - 1), c0, true, ka); // re-formed below at x = 0
+        CellS c0 = cell(0);
+        FaceS fm = face_s<false>(cell(-1), c0, true, ka); // re-formed below at x = 0
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
             const int gp = p0 + k;
-            const CellS cp = cell(gp + 1);
+            const CellS cp = cell(k + 1);
             const FaceS fp = face_s<false>(c0, cp, !(re && k == CPL - 1), ka);
             Band B = xr_band(fm, fp);
             double rhs = wr[k];
@@ -381,13 +381,12 @@ __device__ __forceinline__ void xrow_body(const PassParams &p, const XRowGeom &g
     if (act) {
         xr_record(rec, S, s, fa, fb, fz, fph, fps);
 #pragma unroll
-        for (int k = 0; k < CPL; ++k)
-            if (!lnear || p0 + k >= 0) sU[xr_pad(p0 + k)] = fps[k];
+        for (int k = 0; k < CPL; ++k) sU[base + k] = fps[k];
     }
     __syncthreads();
     xr_tree(rec, S, tr, row_ok);
     // back-substitution from the outer pairs; v replaces the parked factor in the u row
-    if (act) xr_backsub(rec, S, s, p0, lnear, sU, fa, fb, fz, fph);
+    if (act) xr_backsub(rec, S, s, sU + base, fa, fb, fz, fph);
     __syncthreads();
 
     // output: u_{k+1} = u_k + v, update ratio, flags, mass diagnostic (coalesced)
@@ -408,7 +407,7 @@ __device__ __forceinline__ void xrow_body(const PassParams &p, const XRowGeom &g
         for (int k = 0; k < XR_STAGE; ++k) {
             const int i = tr + k * nthr;
             if (i < nx) {
-                const double v = sU[xr_pad(i)];
+                const double v = sU[xr_at(i + sh)];
                 const double un = uk[k] + v;
                 emax = fmax(emax, fabs(v) * rcp(fabs(uk[k])));
                 if (!(un > 0.0)) flags |= (un != un || v != v) ? FLAG_NAN : FLAG_NONPOS;
@@ -553,7 +552,6 @@ k_sbline(int nl, int np, const double *bands, const double *rhs, double *out, un
     const int S = g.S;
     const bool act = row_ok && s < S;
     const int p0 = np - CPL * (S - s);
-    const bool lnear = p0 <= 1;
     const size_t N = (size_t)nl * np;
     // element (position q, this line), 0 <= q < np
     auto at = [&](int q) -> size_t { return PM ? (size_t)q * nl + j : (size_t)j * np + q; };
@@ -587,17 +585,16 @@ k_sbline(int nl, int np, const double *bands, const double *rhs, double *out, un
         }
         xr_record(rec, S, s, fa, fb, fz, fph, fps);
 #pragma unroll
-        for (int k = 0; k < CPL; ++k)
-            if (!lnear || p0 + k >= 0) sV[xr_pad(p0 + k)] = fps[k];
+        for (int k = 0; k < CPL; ++k) sV[xr_base(s) + k] = fps[k];
     }
     __syncthreads();
     xr_tree(rec, S, s, row_ok);
-    if (act) xr_backsub(rec, S, s, p0, lnear, sV, fa, fb, fz, fph);
+    if (act) xr_backsub(rec, S, s, sV + xr_base(s), fa, fb, fz, fph);
     __syncthreads();
     double xm = 0.0, om = 0.0;
     if (row_ok) {
         for (int i = s; i < np; i += nthr) {
-            const double x = sV[xr_pad(i)];
+            const double x = sV[xr_at(i + CPL * S - np)];
             const size_t o = at(i);
             if (MODE == 0) {
                 out[o] = x;

@@ -166,11 +166,36 @@ static void check_rows()
         CHECK(fits, "nx=%d LDS %d > %d", nx, g.R * (g.pu + g.p2), xr_lds(g.waves));
         const int p0_lane0 = nx - XR_CPL * g.S;
         CHECK(p0_lane0 <= 0 && p0_lane0 > -XR_CPL, "nx=%d p0=%d", nx, p0_lane0);
-        CHECK(64 * g.W * XR_STAGE >= nx + 4, "nx=%d staging covers %d", nx, 64 * g.W * XR_STAGE);
-        CHECK(xr_pad(nx + 3) < g.pu, "nx=%d u row", nx);                   // staged u row (2 ghosts)
-        CHECK(xr_pad(nx + 1) < g.p2, "nx=%d neighbour rows", nx);          // u(j-1) + u(j+1)
+        const int W16 = XR_CPL * g.S, sh = W16 - nx;
+        // staging: thread i of the row group stages w = i - 2 (u row, -2 .. 16 S + 1) and
+        // w = i - 1 (neighbour rows, -1 .. 16 S) over XR_STAGE rounds of 64 W threads
+        CHECK(64 * g.W * XR_STAGE >= W16 + 4, "nx=%d staging covers %d", nx, 64 * g.W * XR_STAGE);
+        CHECK(xr_at(-2) == 0 && xr_at(W16 + 1) < g.pu, "nx=%d u row", nx);
+        CHECK(xr_at(-1) >= 0 && xr_at(W16) < g.p2, "nx=%d neighbour rows", nx);
         CHECK(NREL * g.S <= g.p2, "nx=%d records", nx);                    // record tree
-        CHECK(xr_pad(nx - 1) < g.pu, "nx=%d solution", nx);                // parked factor / v
+        {
+            // staged positions map to distinct slots; staged cells reflect into the row
+            std::vector<int> seen(g.pu, 0);
+            for (int w = -2; w <= W16 + 1; ++w) {
+                const int a = xr_at(w);
+                if (a >= 0 && a < g.pu) seen[a]++;
+                const int q = w - sh < -2 ? -2 : w - sh, c = crefl(q, nx);
+                CHECK(c >= 0 && c < nx, "nx=%d w=%d reflects to %d", nx, w, c);
+            }
+            for (int a = 0; a < g.pu; ++a) CHECK(seen[a] <= 1, "nx=%d slot %d staged %d times", nx, a, seen[a]);
+        }
+        // a lane's accesses: cells at relative positions t = -1 .. 16 read t - 1 .. t + 1 of the
+        // u row and t of the neighbour rows, at constant offsets of its block; parked factors and
+        // the solution use t = 0 .. 15
+        for (int s = 0; s < g.S; ++s)
+            for (int t = -2; t <= XR_CPL + 1; ++t) {
+                const int a = xr_base(s) + xr_off(t);
+                CHECK(a == xr_at(XR_CPL * s + t), "nx=%d s=%d t=%d offset", nx, s, t);
+                CHECK(a >= 0 && a < g.pu, "nx=%d s=%d t=%d u row index %d", nx, s, t, a);
+                if (t >= -1 && t <= XR_CPL) CHECK(a < g.p2, "nx=%d s=%d t=%d neighbour index %d", nx, s, t, a);
+            }
+        // the output loop reads position i < nx at xr_at(i + sh), inside the lanes' blocks
+        CHECK(xr_at(sh) >= xr_base(0) && xr_at(nx - 1 + sh) < xr_base(g.S - 1) + XR_CPL, "nx=%d output", nx);
         int levels = 0;
         while ((1 << levels) < g.S) ++levels;
         for (int l = 1; l <= levels; ++l) {
