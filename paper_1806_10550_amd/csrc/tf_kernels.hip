@@ -47,8 +47,8 @@ namespace tf {
 // position before the sweeps and enter the b^n of lanes 0 and 63.
 // ------------------------------------------------------------------------------------
 // Value of the next (lane + 1) / previous (lane - 1) lane of the wave by whole-wave DPP
-// shifts (VALU moves, no LDS permute); the edge lanes get 0 (the sweeps use them only
-// for halo lanes).
+// shifts (VALU moves, no LDS permute); the edge lanes get 0 (the y sweep replaces what
+// they would need by the tile-edge correction of b^n).
 __device__ __forceinline__ double dpp_shift(double v, int ctrl)
 {
     // bound_ctrl set: a lane whose source lies outside the wave reads 0, so no "old" value
