@@ -28,6 +28,20 @@ def test_print_hash_matches_kernel_sources():
     assert r.stdout.strip() == bench.kernel_hash()
 
 
+def test_kernel_hash_ignores_comments_and_layout_but_not_code(tmp_path, monkeypatch):
+    """The hash tagging the committed counter records follows the kernel code: comments and
+    layout do not change it, a changed token does."""
+    src = tmp_path / "k.hip"
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", ["k.hip"])
+    src.write_text("__global__ void k(double *x)\n{\n    x[0] = 2.0 * x[1]; // twice\n}\n")
+    h0 = bench.kernel_hash()
+    src.write_text("/* a kernel */\n__global__ void k(double *x) {\n  x[0] = 2.0 * x[1];  // doubled\n\n}\n")
+    assert bench.kernel_hash() == h0
+    src.write_text("__global__ void k(double *x)\n{\n    x[0] = 3.0 * x[1]; // twice\n}\n")
+    assert bench.kernel_hash() != h0
+
+
 def _hashes():
     out = {}
     for name in ("traffic_large8192.json", "sq_large8192.json"):
