@@ -244,7 +244,8 @@ tf_status tf_ensemble_film_info(const tf_ensemble *e, int film, tf_step_info *in
  *     (I + theta dt J_D(u^{n+1}))^T mu = lambda^{n+1}
  * by Richardson iteration preconditioned with the transposed ADI factors
  * (I + c J_y)^-T (I + c J_x)^-T (eqs. DirectionSplit, JacobianSystem1-2) until
- * max|dmu| <= tol max|mu| (at most max_iter iterations; TF_ENOCONV otherwise), then
+ * max|dmu| <= tol max|mu| (at most max_iter iterations; TF_ENOCONV otherwise, TF_ENONPOS if
+ * an iterate turns NaN), then
  * writes lambda^n = mu - (1-theta) dt J_D(u^n)^T mu into lambda_inout and adds
  * -dt mu . [theta dD/dkappa(u^{n+1}) + (1-theta) dD/dkappa(u^n)] to *dL_dkappa_accum
  * (host, nullable; power-law model only, TF_EINVAL for the linear, NLC and polymer models). h_n, h_np1: the two time levels (device, nx*ny each, unchanged).
